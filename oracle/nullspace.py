@@ -30,9 +30,18 @@ def nullspace(G, rank):
     """Eigendecomposition of the Hermitian Gram G.
 
     Returns ``(Q, evals, U)``: eigenvalues ascending, U the full set of
-    eigenvectors, and Q = U[:, :n - rank] (the n - rank smallest)."""
+    eigenvectors, and Q = U[:, :n - rank] (the n - rank smallest).
+
+    The paper leaves the basis free (any unitary mix of Q gives the same
+    objective); to make JL draws comparable across implementations each
+    eigenvector is multiplied by the unit phase that makes the sum of its
+    entries real and non-negative."""
     n = G.shape[0]
     if not 0 <= rank < n:
         raise ValueError("rank must satisfy 0 <= r < n")
     evals, U = np.linalg.eigh(G)
+    tot = U.sum(axis=0)
+    mag = np.abs(tot)
+    ph = np.where(mag > 0, np.conj(tot) / np.where(mag > 0, mag, 1.0), 1.0)
+    U = U * ph[None, :]
     return U[:, : n - rank], evals, U
