@@ -1,0 +1,215 @@
+/*
+ * hicu.h — C ABI of the MI355X HICU hot-path library (libhicu.so).
+ *
+ * HICU (Zhao, Potter, Ahmad: "High-dimensional fast convolutional framework
+ * for calibrationless MRI") recovers unobserved k-space by alternating
+ * between a nullspace (annihilating-filter) estimate and gradient steps on
+ * the residual energy of the multi-coil valid convolution (Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named *_dev are DEVICE pointers on the current HIP device;
+ *   pointers named *_host are host pointers.  The caller allocates and owns
+ *   every buffer; the library never frees or retains caller buffers.
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Calls enqueue work and return, except where "synchronous" is stated.
+ *   Scalar results (J, ||g||^2, eta) are written to device memory so that a
+ *   loop of calls needs no host synchronisation.
+ * - Complex data are interleaved (re, im) pairs: complex64 = 2 x float,
+ *   complex128 = 2 x double.
+ * - k-space x is stored [d0][d1][d2][c] (coil c fastest, "coil-interleaved");
+ *   spatial axes with index 0 slowest.  Fewer than three spatial axes are
+ *   expressed with leading extents of 1 (see hicu_geom).
+ * - Arguments are validated before any launch; on error nothing is written
+ *   and a negative hicu_status is returned.  HIP runtime failures map to
+ *   HICU_ERR_HIP.  No exception crosses this boundary.
+ */
+#ifndef HICU_H
+#define HICU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HICU_OK = 0,
+  HICU_CONVERGED = 1,          /* informational: gradient is exactly zero */
+  HICU_ERR_ARG = -1,           /* NULL pointer / bad enum / bad count */
+  HICU_ERR_SHAPE = -2,         /* inconsistent geometry, region smaller than kernel */
+  HICU_ERR_RANK = -3,          /* rank outside [0, n) or p outside its range */
+  HICU_ERR_NONFINITE = -4,     /* a NaN/Inf reached a scalar the loop depends on */
+  HICU_ERR_HIP = -5,           /* HIP runtime error */
+  HICU_ERR_WORKSPACE = -6,     /* workspace missing or too small */
+  HICU_ERR_UNSUPPORTED = -7,   /* valid request this build does not implement */
+  HICU_ERR_NOCONV = -8         /* eigensolver hit its sweep limit */
+} hicu_status;
+
+/* Operand precision of the im2col contractions (forward convolution,
+ * adjoint convolution, line-search convolution).  Accumulation is always
+ * FP32; scalar reductions finish in FP64.
+ *   HICU_FP32   FP32 operands on the FP32 matrix cores.
+ *   HICU_BF16   BF16 operands (round-to-nearest-even), one MFMA per tile.
+ *   HICU_BF16X3 each FP32 operand split into hi + lo BF16 parts, three
+ *               MFMAs (hi*hi + hi*lo + lo*hi) per tile: ~16-bit mantissa. */
+typedef enum { HICU_FP32 = 0, HICU_BF16 = 1, HICU_BF16X3 = 2 } hicu_prec;
+
+/* Problem geometry (THEORY section: k-space array, kernel mask, region S).
+ * ndim      1..3 spatial axes.  Entries of dims/kdims/lo/hi beyond ndim are
+ *           ignored; axes are right-aligned internally, i.e. a 2-D problem
+ *           [d0][d1][c] is handled as [1][d0][d1][c].
+ * nchan     coils Nc >= 1; the kernel always spans all coils, so one valid
+ *           convolution also sums over coils.
+ * dims      array extents.
+ * kdims     rectangular kernel box; n = prod(kdims) * nchan taps.
+ * lo, hi    region S = [lo, hi) per axis on which H is built (the centre-out
+ *           box or the whole array); requires 0 <= lo, hi <= dims,
+ *           hi - lo >= kdims.  Valid outputs u satisfy lo <= u <= hi - K. */
+typedef struct {
+  int32_t ndim;
+  int32_t nchan;
+  int64_t dims[3];
+  int32_t kdims[3];
+  int64_t lo[3];
+  int64_t hi[3];
+} hicu_geom;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t hicu_version(void);
+
+/* Static description of a status code. */
+const char* hicu_status_string(int32_t status);
+
+/* Number of taps n = prod(kdims) * nchan, or a negative status. */
+int64_t hicu_num_taps(const hicu_geom* geom);
+
+/* Number of valid outputs s of region S, or a negative status. */
+int64_t hicu_num_outputs(const hicu_geom* geom);
+
+/* ------------------------------------------------------------------------
+ * Gram matrix G = H_S(x)' H_S(x)   (DISCUSSION: Gram-matrix route to the
+ * nullspace; THEORY: H(x) is the multi-level Hankel matrix of x on S).
+ *   G[(k,c),(k',c')] = sum_{u valid} conj(x[u+k, c]) * x[u+k', c']
+ * Row/column index = (k0, k1, k2, c) lexicographic, coil fastest.
+ * x_dev   complex64 array of the full geometry.
+ * G_dev   complex128 n x n, row-major, both triangles written.
+ * Products and accumulation are FP64 (x is read as FP32 and widened).
+ * ws_dev  device workspace of at least hicu_gram_workspace_bytes(geom).
+ * ------------------------------------------------------------------------ */
+size_t hicu_gram_workspace_bytes(const hicu_geom* geom);
+int32_t hicu_gram(const hicu_geom* geom, const void* x_dev, void* G_dev,
+                  void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Nullspace basis from the Gram (THEORY: J(x) of Eq. 1 equals
+ * min ||H(x) Q||_F^2 over orthonormal Q with n - r columns; Algorithm 1,
+ * nullspace update).  FP64 Hermitian eigendecomposition on the device by
+ * block-Jacobi.
+ * G_dev      complex128 n x n Hermitian (read only).
+ * V0_dev     optional complex128 n x n unitary warm start (e.g. the previous
+ *            call's eigenvectors), NULL for identity.
+ * Q_dev      complex64 n x (n - r) row-major: eigenvectors of the n - r
+ *            smallest eigenvalues in ascending order, each scaled by a unit
+ *            phase so that the sum of its entries is real and >= 0.
+ * evals_dev  optional double[n], all eigenvalues ascending.
+ * V_dev      optional complex128 n x n, all eigenvectors (columns, same
+ *            order and phase rule as Q), usable as the next warm start.
+ * sweeps_host optional: number of Jacobi sweeps used.
+ * Synchronous on `stream` (the convergence test reads one flag per sweep).
+ * Returns HICU_ERR_NOCONV if 40 sweeps do not reach relative off-diagonal
+ * size 1e-14 (outputs are still written).
+ * ------------------------------------------------------------------------ */
+size_t hicu_nullspace_workspace_bytes(int32_t n);
+int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G_dev, const void* V0_dev,
+                       void* Q_dev, double* evals_dev, void* V_dev, int32_t* sweeps_host,
+                       void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * JL compression F = Q P   (THEORY: second numerical technique; Algorithm 1,
+ * JL step).  P is real (nq x p), i.i.d. N(0, 1/p), drawn on the device from
+ * Philox4x32-10 with key (seed lo, seed hi) and counter
+ * (element/4, outer, inner, stream_id); each 4-word block gives four normals
+ * by Box-Muller with u = (w + 1/2) 2^-32.
+ * Q_dev  complex64 n x nq row-major; F_dev complex64 n x p row-major.
+ * P_dev  optional double nq x p output of the drawn matrix (for checking).
+ * ------------------------------------------------------------------------ */
+int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q_dev,
+                         uint64_t seed, uint32_t outer, uint32_t inner, uint32_t stream_id,
+                         void* F_dev, double* P_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Objective and gradient (THEORY: Eq. 2 with hard data matching; Algorithm 1
+ * gradient step).  With Y = H_S(x) F:
+ *   J      = ||Y||_F^2
+ *   g      = 2 (1 - M) o H_S'(Y F^H)      (= 2 dJ/d conj(x), zero at observed
+ *                                          locations and outside S)
+ *   gnorm2 = ||g||^2
+ * x_dev     complex64 full array.
+ * mask_dev  uint8 [d0][d1][d2], 1 = observed (broadcast over coils); NULL =
+ *           nothing observed.
+ * F_dev     complex64 n x p row-major (filters in columns).
+ * J_dev, g_dev, gnorm2_dev  outputs; any may be NULL (g_dev NULL skips the
+ *           adjoint).  J_dev/gnorm2_dev are single doubles.
+ * ws_dev    at least hicu_workspace_bytes(geom, p, prec) bytes.
+ * ------------------------------------------------------------------------ */
+size_t hicu_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
+int32_t hicu_objective_grad(const hicu_geom* geom, const void* x_dev, const uint8_t* mask_dev,
+                            const void* F_dev, int32_t p, int32_t prec, double* J_dev,
+                            void* g_dev, double* gnorm2_dev, void* ws_dev, size_t ws_bytes,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Exact line search (THEORY: third numerical technique; Algorithm 1 ELS
+ * step).  Z = H_S(g) F;  eta = gnorm2 / (2 ||Z||_F^2), eta = 0 when Z = 0.
+ * gnorm2_dev  device double from hicu_objective_grad.
+ * eta_dev     device double output.
+ * ------------------------------------------------------------------------ */
+int32_t hicu_line_search(const hicu_geom* geom, const void* g_dev, const double* gnorm2_dev,
+                         const void* F_dev, int32_t p, int32_t prec, double* eta_dev,
+                         void* ws_dev, size_t ws_bytes, void* stream);
+
+/* x <- x - eta g over the whole array (Algorithm 1 update); eta read from
+ * device memory.  Observed entries stay bit-identical because g is zero
+ * there. */
+int32_t hicu_update(const hicu_geom* geom, void* x_dev, const void* g_dev,
+                    const double* eta_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Full reconstruction, Algorithm 1 (Gram-eigendecomposition nullspace route).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t rank;             /* r: 0 <= r < n */
+  int32_t p;                /* filters per step: 0 = whole nullspace (no JL), else JL to p */
+  int32_t n_outer;          /* I */
+  int32_t start_outer;      /* resume: first outer iteration to run (0-based) */
+  const int32_t* steps;     /* host int32[n_outer]: G^(i) gradient steps */
+  const int64_t* regions;   /* host int64[n_outer][6]: lo[0..2] then hi[0..2], the first ndim
+                               entries of each used as in hicu_geom; NULL = whole array */
+  uint64_t seed;            /* JL seed */
+  int32_t prec;             /* hicu_prec of the contractions */
+  int32_t refine_steps;     /* the last refine_steps gradient steps of the run use HICU_FP32 */
+  int32_t warm_start;       /* 1: start each eigensolve from the previous eigenvectors */
+} hicu_params;
+
+/* One record per gradient step, filled when trace_host != NULL
+ * (host array of sum(steps[start_outer..]) records). */
+typedef struct {
+  int32_t outer, inner, prec, sweeps;
+  double J, gnorm2, eta;
+} hicu_trace;
+
+/* x0_dev    complex64 zero-filled observations (full array).
+ * mask_dev  uint8 observed mask (may be NULL).
+ * x_out_dev complex64 result; may alias x0_dev.
+ * Allocates its own device workspace for the call.  Synchronous. */
+int32_t hicu_solve(const hicu_geom* geom, const void* x0_dev, const uint8_t* mask_dev,
+                   const hicu_params* params, void* x_out_dev, hicu_trace* trace_host,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HICU_H */

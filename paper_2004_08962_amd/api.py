@@ -1,0 +1,191 @@
+"""Thin torch-facing binding of libhicu.so: argument marshalling only.
+
+Every array is a CUDA (HIP) torch tensor on the current device; k-space is
+complex64 of shape (D0, D1, D2, Nc) (2-D data with D0 = 1), masks uint8 of
+shape (D0, D1, D2).  Work is enqueued on torch's current stream.  All
+arithmetic happens in the library's HIP kernels.
+"""
+import ctypes
+
+import torch
+
+from ._lib import Geom, Params, Trace, PREC, check, load
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def geom(shape, kdims, lo=None, hi=None):
+    """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box."""
+    d = [int(v) for v in shape[:3]]
+    g = Geom()
+    g.ndim = 3
+    g.nchan = int(shape[3])
+    lo = (0, 0, 0) if lo is None else lo
+    hi = d if hi is None else hi
+    for a in range(3):
+        g.dims[a] = d[a]
+        g.kdims[a] = int(kdims[a])
+        g.lo[a] = int(lo[a])
+        g.hi[a] = int(hi[a])
+    return g
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PREC[p]
+    return int(p)
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def num_taps(shape, kdims):
+    return int(load().hicu_num_taps(ctypes.byref(geom(shape, kdims))))
+
+
+def gram(x, kdims, lo=None, hi=None):
+    """G = H_S(x)' H_S(x) as complex128 (n, n)."""
+    lib = load()
+    _dev(x, torch.complex64, "x")
+    g = geom(x.shape, kdims, lo, hi)
+    n = int(lib.hicu_num_taps(ctypes.byref(g)))
+    check(n, "hicu_num_taps")
+    G = torch.empty((n, n), dtype=torch.complex128, device=x.device)
+    wsb = lib.hicu_gram_workspace_bytes(ctypes.byref(g))
+    ws = _workspace(wsb, x.device)
+    check(lib.hicu_gram(ctypes.byref(g), _ptr(x), _ptr(G), _ptr(ws), wsb, _stream()), "hicu_gram")
+    return G
+
+
+def nullspace(G, rank, V0=None, want_V=True):
+    """Returns (Q complex64 (n, n-r), evals float64 (n,), V complex128 or None, sweeps)."""
+    lib = load()
+    _dev(G, torch.complex128, "G")
+    n = G.shape[0]
+    if V0 is not None:
+        _dev(V0, torch.complex128, "V0")
+    Q = torch.empty((n, n - rank), dtype=torch.complex64, device=G.device)
+    ev = torch.empty((n,), dtype=torch.float64, device=G.device)
+    V = torch.empty((n, n), dtype=torch.complex128, device=G.device) if want_V else None
+    sweeps = ctypes.c_int32(0)
+    wsb = lib.hicu_nullspace_workspace_bytes(n)
+    ws = _workspace(wsb, G.device)
+    check(lib.hicu_nullspace(n, int(rank), _ptr(G), _ptr(V0), _ptr(Q), _ptr(ev), _ptr(V), ctypes.byref(sweeps),
+                             _ptr(ws), wsb, _stream()), "hicu_nullspace")
+    return Q, ev, V, int(sweeps.value)
+
+
+def jl_compress(Q, p, seed, outer, inner, stream_id=0, return_P=False):
+    """F = Q P with P drawn on the device (Philox4x32-10 + Box-Muller)."""
+    lib = load()
+    _dev(Q, torch.complex64, "Q")
+    n, nq = Q.shape
+    F = torch.empty((n, p), dtype=torch.complex64, device=Q.device)
+    P = torch.empty((nq, p), dtype=torch.float64, device=Q.device) if return_P else None
+    check(lib.hicu_jl_compress(n, nq, int(p), _ptr(Q), int(seed), int(outer), int(inner), int(stream_id),
+                               _ptr(F), _ptr(P), _stream()), "hicu_jl_compress")
+    return (F, P) if return_P else F
+
+
+def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None):
+    return int(load().hicu_workspace_bytes(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec)))
+
+
+def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=True, ws=None):
+    """Returns (J, g, gnorm2): J and gnorm2 are 0-dim float64 CUDA tensors,
+    g complex64 like x (None when want_grad is False)."""
+    lib = load()
+    _dev(x, torch.complex64, "x")
+    _dev(F, torch.complex64, "F")
+    if mask is not None:
+        _dev(mask, torch.uint8, "mask")
+    g = geom(x.shape, kdims, lo, hi)
+    p = F.shape[1]
+    wsb = lib.hicu_workspace_bytes(ctypes.byref(g), p, _prec(prec))
+    if wsb == 0:
+        raise ValueError("unsupported geometry / filter count")
+    ws = _workspace(wsb, x.device) if ws is None else ws
+    J = torch.empty((), dtype=torch.float64, device=x.device)
+    gout = torch.empty_like(x) if want_grad else None
+    gn2 = torch.empty((), dtype=torch.float64, device=x.device) if want_grad else None
+    check(lib.hicu_objective_grad(ctypes.byref(g), _ptr(x), _ptr(mask), _ptr(F), p, _prec(prec), _ptr(J), _ptr(gout),
+                                  _ptr(gn2), _ptr(ws), ws.numel(), _stream()), "hicu_objective_grad")
+    return J, gout, gn2
+
+
+def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None):
+    """eta = ||g||^2 / (2 ||H(g) F||^2) as a 0-dim float64 CUDA tensor."""
+    lib = load()
+    _dev(gv, torch.complex64, "g")
+    _dev(F, torch.complex64, "F")
+    _dev(gnorm2, torch.float64, "gnorm2")
+    g = geom(gv.shape, kdims, lo, hi)
+    p = F.shape[1]
+    wsb = lib.hicu_workspace_bytes(ctypes.byref(g), p, _prec(prec))
+    ws = _workspace(wsb, gv.device) if ws is None else ws
+    eta = torch.empty((), dtype=torch.float64, device=gv.device)
+    check(lib.hicu_line_search(ctypes.byref(g), _ptr(gv), _ptr(gnorm2), _ptr(F), p, _prec(prec), _ptr(eta),
+                               _ptr(ws), ws.numel(), _stream()), "hicu_line_search")
+    return eta
+
+
+def update(x, gv, eta, kdims=(1, 1, 1)):
+    """In place: x <- x - eta g."""
+    lib = load()
+    _dev(x, torch.complex64, "x")
+    _dev(gv, torch.complex64, "g")
+    _dev(eta, torch.float64, "eta")
+    g = geom(x.shape, kdims)
+    check(lib.hicu_update(ctypes.byref(g), _ptr(x), _ptr(gv), _ptr(eta), _stream()), "hicu_update")
+    return x
+
+
+def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_steps=0, warm_start=True,
+          start_outer=0, out=None):
+    """Algorithm 1 on the device.  ``schedule``: list of (lo, hi, steps).
+    Returns (x, trace) with trace a list of dicts (one per gradient step)."""
+    lib = load()
+    _dev(x0, torch.complex64, "x0")
+    if mask is not None:
+        _dev(mask, torch.uint8, "mask")
+    g = geom(x0.shape, kdims)
+    n_outer = len(schedule)
+    steps = (ctypes.c_int32 * max(1, n_outer))(*[int(s[2]) for s in schedule])
+    regs = (ctypes.c_int64 * max(1, 6 * n_outer))(
+        *[int(v) for (lo, hi, _) in schedule for v in list(lo) + list(hi)])
+    prm = Params()
+    prm.rank = int(rank)
+    prm.p = int(p)
+    prm.n_outer = n_outer
+    prm.start_outer = int(start_outer)
+    prm.steps = ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32))
+    prm.regions = ctypes.cast(regs, ctypes.POINTER(ctypes.c_int64))
+    prm.seed = int(seed)
+    prm.prec = _prec(prec)
+    prm.refine_steps = int(refine_steps)
+    prm.warm_start = 1 if warm_start else 0
+    total = sum(int(s[2]) for s in schedule[start_outer:])
+    tr = (Trace * max(1, total))()
+    x = torch.empty_like(x0) if out is None else out
+    check(lib.hicu_solve(ctypes.byref(g), _ptr(x0), _ptr(mask), ctypes.byref(prm), _ptr(x), tr, _stream()),
+          "hicu_solve")
+    trace = [dict(outer=t.outer, inner=t.inner, prec=t.prec, sweeps=t.sweeps, J=t.J, gnorm2=t.gnorm2, eta=t.eta)
+             for t in tr[:total]]
+    return x, trace

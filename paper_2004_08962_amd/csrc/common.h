@@ -1,0 +1,92 @@
+// Shared helpers for the HICU HIP library (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "hicu.h"
+
+namespace hicu {
+
+// ---------------------------------------------------------------------------
+// Error plumbing (host)
+// ---------------------------------------------------------------------------
+#define HICU_HIP_TRY(expr)                                  \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return HICU_ERR_HIP;              \
+  } while (0)
+
+#define HICU_TRY(expr)                                      \
+  do {                                                      \
+    int32_t _s = (expr);                                    \
+    if (_s < 0) return _s;                                  \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Canonical (right-aligned, 3-axis) geometry
+// ---------------------------------------------------------------------------
+struct Geo {
+  int64_t d[3];   // array extents
+  int nc;         // coils
+  int k[3];       // kernel box
+  int64_t lo[3], hi[3];
+  int64_t m[3];   // valid extents of region: hi - lo - k + 1
+  int64_t s;      // number of valid outputs
+  int64_t npts;   // spatial points of the array
+  int n;          // taps = k0 k1 k2 nc
+};
+
+int32_t make_geo(const hicu_geom* g, Geo* out);
+
+// ---------------------------------------------------------------------------
+// Precision modes of the contraction kernels
+// ---------------------------------------------------------------------------
+enum { P_F32 = 0, P_BF16 = 1, P_BF16X3 = 2 };
+
+// Reduction elements per k-block: FP32 uses four 16x16x4 MFMAs per block of
+// 16, BF16 one 16x16x32 MFMA per block of 32.
+__host__ __device__ constexpr int kblock_of(int prec) { return prec == P_F32 ? 16 : 32; }
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ double warp_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block reduction of one double per thread (blockDim.x <= 1024,
+// multiple of 64).  Result valid in thread 0.
+__device__ __forceinline__ double block_sum_d(double v, double* sh) {
+  v = warp_sum_d(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+}  // namespace hicu

@@ -1,0 +1,94 @@
+// Valid multi-channel correlation on MFMA: the im2col contraction behind the
+// forward convolution H(x)F, the adjoint H'(Y F^H) and the line-search
+// convolution H(g)F (THEORY section: HICU relies exclusively on these
+// multi-dimensional convolutions).
+#pragma once
+
+#include "common.h"
+
+namespace hicu {
+
+// One launch computes, for every output position u in a box of extents oe
+// and every real output column n in [col0, col0 + coutr):
+//   out[u, n] = scale * sum_{k in kernel box} sum_{e} in[org + u + k, e] * W[k, e, n]
+// where e runs over the real (re, im) entries of the input channels and
+// input points outside the validity box [vlo, vhi) read as zero.  Optional
+// epilogue: zero at masked positions, add to the existing output, and a
+// per-block sum of squares of the final values.
+struct ConvArgs {
+  const float2* in;
+  int64_t is[3];          // input strides (complex elements) per spatial axis
+  int cin;                // input complex channels (channel stride 1)
+  int chunk_c;            // complex channels per LDS chunk
+  int nchunks;            // chunks processed by this launch
+  int ch0;                // first input chunk (and weight chunk) of this launch
+  int ps;                 // LDS elements per point (>= 2*chunk_c, multiple of 8)
+  int nkb;                // k-blocks per contiguous run of k2*ps elements
+  int rs;                 // LDS elements per halo row
+  int h[3];               // halo extents
+  int64_t vlo[3], vhi[3];
+  int64_t org[3];
+  int64_t oe[3];          // output extents
+  int64_t nt[3];          // tiles per axis
+  int k[3];
+  const void* B;          // weights [chunk][k0][k1][kb][ncolp][KB]
+  const void* Blo;        // low parts for the split precision
+  int ncolp;              // padded weight columns
+  int col0;               // first weight column of this launch
+  int coutr;              // real output columns written by this launch
+  float* out;             // real view of complex output, may be null
+  int64_t os[3];          // output strides (complex elements)
+  const uint8_t* mask;    // may be null
+  int64_t ms[3];
+  int64_t morg[3];        // mask coordinate of output position 0
+  float scale;
+  int accumulate;
+  double* partial;        // per-block sum of squares, may be null
+};
+
+// Tile shape: T0 positions along axis 0, 16 along axis 1, T2 along axis 2
+// (T0*T2 must be a multiple of 4: one or more 16-position MFMA row fragments
+// per wave), WN 16-column fragments per wave.
+struct TileCfg {
+  int T0, T2, WN;
+};
+
+struct ConvPlan {
+  int prec;
+  TileCfg t;
+  ConvArgs a;
+  dim3 grid;
+  size_t lds_bytes;
+};
+
+// Weight layout of one contraction (shared by the weight builder and the
+// convolution kernel).
+struct WeightShape {
+  int chunk_c, nchunks, ps, nkb, ncolp, KB;
+  size_t elems;           // elements per part (hi or lo)
+};
+
+constexpr int kColPad = 64;  // weight columns padded to the widest tile
+
+WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total);
+
+// Build weights from the filter matrix F (n x p complex64, row-major).
+//   mode 0 (forward):  input channels = coils, output columns = (filter, re/im)
+//   mode 1 (adjoint):  input channels = filters, output columns = (coil, re/im),
+//                      taps flipped and conjugated.
+int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, int p,
+                            const WeightShape& ws, void* B, void* Blo, hipStream_t st);
+
+TileCfg default_tile(int prec, const Geo& g, int coutr);
+
+// Fill the shape-dependent fields of plan->a (everything but pointers,
+// strides, org, validity box and epilogue options).
+int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, int nchunks,
+                  const int64_t oe[3], int coutr, ConvPlan* plan);
+
+int32_t launch_conv(const ConvPlan& plan, hipStream_t st);
+
+// Fixed-order sum of `count` doubles into *out (single block).
+int32_t launch_reduce(const double* part, int64_t count, double* out, hipStream_t st);
+
+}  // namespace hicu

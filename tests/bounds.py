@@ -1,0 +1,85 @@
+"""Rounding-error bounds for comparing the HIP contractions with the FP64
+oracle element by element.
+
+For a sum of products s = sum_i a_i b_i evaluated with operands rounded to
+a format of unit roundoff u_op and accumulated in a format of unit
+roundoff u_acc, |fl(s) - s| <= (2 u_op + u_op^2 + T u_acc) sum_i |a_i b_i|
+(T = number of real terms; standard forward bound, Higham ch. 3).  The
+magnitude sums are obtained by running the oracle's contractions on
+absolute values.  Bounds are worst case; observed errors are much smaller.
+"""
+import numpy as np
+
+import oracle
+
+U32 = 2.0 ** -24
+# Operand representation error per precision mode: FP32 inputs are exact,
+# BF16 rounds to 8 significant bits, the split hi+lo BF16 pair keeps ~16 bits
+# and drops the lo*lo product.
+U_OP = {"fp32": 0.0, "bf16": 2.0 ** -8, "bf16x3": 3.0 * 2.0 ** -16}
+
+
+def _ops_factor(prec, terms):
+    u = U_OP[prec]
+    return 2.0 * u + u * u + terms * U32
+
+
+def forward_bound(x, F, kd, lo, hi, prec):
+    """Elementwise bound on |Y_gpu - Y| for Y = H(x) F; also returns Y."""
+    n = F.shape[0]
+    Y = oracle.forward(x, F, kd, lo, hi)
+    Yabs = oracle.forward(np.abs(x), np.abs(F), kd, lo, hi).real
+    return Y, _ops_factor(prec, 2 * n + 2) * Yabs
+
+
+def grad_bound(x, mask, F, kd, lo, hi, prec):
+    """Elementwise bound on |g_gpu - g| for g = 2 (1-M) o H'(Y F^H), with the
+    propagated error of the stored Y (rounded to FP32) included."""
+    p = F.shape[1]
+    K = kd[0] * kd[1] * kd[2]
+    Y, eY = forward_bound(x, F, kd, lo, hi, prec)
+    eY = eY + U32 * np.abs(Y)
+    Fa = np.abs(F)
+    shape = x.shape
+    prop = 2.0 * oracle.hankel_adjoint(eY @ Fa.T, shape, kd, lo, hi).real
+    mag = 2.0 * oracle.hankel_adjoint(np.abs(Y) @ Fa.T, shape, kd, lo, hi).real
+    b = prop + _ops_factor(prec, 2 * K * p + 2) * mag
+    if mask is not None:
+        b[np.asarray(mask).astype(bool)] = 0.0
+    return b
+
+
+def sumsq_bound(v, ev):
+    """Bound on |sum|v_gpu|^2 - sum|v|^2| given |v_gpu - v| <= ev."""
+    return float(np.sum(2.0 * np.abs(v) * ev + ev * ev)) + 1e-12 * float(np.sum(np.abs(v) ** 2))
+
+
+def grad_bound_at_points(x, F, kd, lo, hi, prec, points):
+    """grad_bound evaluated only at k-space locations ``points`` (mask not
+    applied), from the point-wise oracle routines on absolute values."""
+    p = F.shape[1]
+    K = kd[0] * kd[1] * kd[2]
+    n = F.shape[0]
+    nc = x.shape[3]
+    Fa = np.abs(F)
+    xa = np.abs(x)
+    f1 = _ops_factor(prec, 2 * n + 2)
+    f2 = _ops_factor(prec, 2 * K * p + 2)
+    out = np.zeros((len(points), nc))
+    for idx, w in enumerate(points):
+        acc_mag = np.zeros(nc)
+        acc_abs = np.zeros(nc)
+        t = 0
+        for k0 in range(kd[0]):
+            for k1 in range(kd[1]):
+                for k2 in range(kd[2]):
+                    u = (w[0] - k0, w[1] - k1, w[2] - k2)
+                    if all(lo[a] <= u[a] <= hi[a] - kd[a] for a in range(3)):
+                        y = np.abs(oracle.residual_at_points(x, F, kd, [u])[0])
+                        ya = oracle.residual_at_points(xa, Fa, kd, [u])[0].real
+                        Ft = Fa[t * nc:(t + 1) * nc, :]
+                        acc_mag += Ft @ y
+                        acc_abs += Ft @ ya
+                    t += 1
+        out[idx] = 2.0 * (f1 * acc_abs + U32 * acc_mag) + f2 * 2.0 * acc_mag
+    return out

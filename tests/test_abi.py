@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments before touching a device (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hicu.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hicu_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2004_08962_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libhicu.so not built: run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    from paper_2004_08962_amd import _lib
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, "binding misses " + n
+
+
+def _geom(dims=(1, 64, 64), nc=4, k=(1, 5, 5), lo=(0, 0, 0), hi=None):
+    from paper_2004_08962_amd._lib import Geom
+    g = Geom()
+    g.ndim, g.nchan = 3, nc
+    hi = dims if hi is None else hi
+    for a in range(3):
+        g.dims[a], g.kdims[a], g.lo[a], g.hi[a] = dims[a], k[a], lo[a], hi[a]
+    return g
+
+
+def test_counts_and_status_strings(lib):
+    g = _geom()
+    assert lib.hicu_num_taps(ctypes.byref(g)) == 100
+    assert lib.hicu_num_outputs(ctypes.byref(g)) == 60 * 60
+    assert lib.hicu_version() >= 100
+    assert lib.hicu_status_string(-6) == b"workspace missing or too small"
+    g2 = _geom(dims=(64, 64, 4), k=(5, 5, 1))   # trailing singleton axis is fine
+    assert lib.hicu_num_taps(ctypes.byref(g2)) == 100
+    # 2-D given with ndim = 2 is right-aligned internally
+    g3 = _geom()
+    g3.ndim = 2
+    g3.dims[0], g3.dims[1], g3.kdims[0], g3.kdims[1] = 64, 64, 5, 5
+    g3.lo[0] = g3.lo[1] = 0
+    g3.hi[0], g3.hi[1] = 64, 64
+    assert lib.hicu_num_outputs(ctypes.byref(g3)) == 3600
+
+
+@pytest.mark.parametrize("kw", [
+    dict(k=(1, 5, 70)),                          # kernel larger than region
+    dict(lo=(0, 10, 10), hi=(1, 13, 40)),        # region smaller than kernel
+    dict(hi=(1, 65, 64)),                        # region beyond array
+    dict(lo=(0, -1, 0)),
+])
+def test_bad_geometry_rejected(lib, kw):
+    g = _geom(**kw)
+    assert lib.hicu_num_taps(ctypes.byref(g)) == -2
+    assert lib.hicu_gram(ctypes.byref(g), None, None, None, 0, None) == -2
+
+
+def test_bad_arguments_rejected_before_launch(lib):
+    g = _geom()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.hicu_gram(ctypes.byref(g), None, fake, None, 0, None) == -1
+    assert lib.hicu_gram(ctypes.byref(g), fake, fake, None, 0, None) == -6
+    assert lib.hicu_objective_grad(ctypes.byref(g), fake, None, fake, 0, 0, None, None, None, None, 0, None) == -3
+    assert lib.hicu_objective_grad(ctypes.byref(g), fake, None, fake, 8, 7, None, None, None, None, 0, None) == -1
+    assert lib.hicu_objective_grad(ctypes.byref(g), fake, None, fake, 8, 0, None, fake, None, None, 0, None) == -6
+    assert lib.hicu_nullspace(100, 100, fake, None, fake, None, None, None, None, 0, None) == -3
+    assert lib.hicu_nullspace(100, -1, fake, None, fake, None, None, None, None, 0, None) == -3
+    assert lib.hicu_nullspace(100, 30, fake, None, fake, None, None, None, None, 0, None) == -6
+    assert lib.hicu_line_search(ctypes.byref(g), fake, None, fake, 8, 0, fake, None, 0, None) == -1
+    assert lib.hicu_jl_compress(100, 70, 0, fake, 1, 0, 0, 0, fake, None, None) == -1
+
+
+def test_workspace_sizes(lib):
+    g = _geom(dims=(1, 256, 232), nc=16)
+    s = 252 * 228
+    for prec in (0, 1, 2):
+        b = lib.hicu_workspace_bytes(ctypes.byref(g), 280, prec)
+        assert b >= s * 280 * 8            # holds the residual Y
+        assert b < s * 280 * 8 + (64 << 20)
+    assert lib.hicu_gram_workspace_bytes(ctypes.byref(g)) > 0
+    assert lib.hicu_nullspace_workspace_bytes(400) >= 4 * 416 * 416 * 16
+    assert lib.hicu_workspace_bytes(ctypes.byref(g), 280, 9) == 0

@@ -1,0 +1,116 @@
+"""GPU reconstructions (Algorithm 1 through hicu_solve) against the FP64
+oracle, and full-size sampled parity at the benchmarked workload."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from bounds import forward_bound, grad_bound_at_points, sumsq_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import torch
+    import paper_2004_08962_amd as hicu
+    assert torch.cuda.is_available()
+    hicu.load()
+    return hicu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def p64():
+    P = synth.make_problem("2d_64x64x4")
+    x0 = P["x0"].astype(np.complex64)
+    ref = oracle.solve(x0.astype(np.complex128), P["mask"], P["kdims"], P["rank"], P["schedule"])
+    return P, x0, ref
+
+
+def test_solve_fp32_matches_oracle(hc, p64):
+    P, x0, ref = p64
+    print("solve fp32 2d_64x64x4", flush=True)
+    x, tr = hc.solve(_dev(x0), _dev(P["mask"]), P["kdims"], P["rank"], P["schedule"], prec="fp32")
+    xh = x.cpu().numpy()
+    err = oracle.rel_err(xh, ref)
+    print("rel err", err, "ser", oracle.ser(xh, P["x_true"]), oracle.ser(ref, P["x_true"]), flush=True)
+    assert err <= 1e-4
+    obs = P["mask"].astype(bool)
+    assert np.array_equal(xh[obs], x0[obs])
+    assert len(tr) == 50
+    # J never increases within an outer iteration (ELS), as in the oracle
+    for a, b in zip(tr[:-1], tr[1:]):
+        if a["outer"] == b["outer"]:
+            assert b["J"] <= a["J"] * (1 + 1e-5)
+    for t in tr:
+        assert np.isfinite(t["J"]) and t["eta"] >= 0
+
+
+@pytest.mark.parametrize("prec,refine,tol_db", [("bf16", 10, 0.1), ("bf16x3", 0, 0.1)])
+def test_solve_low_precision_ser(hc, p64, prec, refine, tol_db):
+    P, x0, ref = p64
+    print("solve", prec, "refine", refine, flush=True)
+    x, tr = hc.solve(_dev(x0), _dev(P["mask"]), P["kdims"], P["rank"], P["schedule"], prec=prec,
+                     refine_steps=refine)
+    xh = x.cpu().numpy()
+    d = oracle.ser(xh, P["x_true"]) - oracle.ser(ref, P["x_true"])
+    print("delta SER", d, "rel err", oracle.rel_err(xh, ref), flush=True)
+    assert abs(d) <= tol_db
+    assert sum(t["prec"] == 0 for t in tr) == refine
+
+
+def test_solve_jl_centre_out_and_resume(hc):
+    P = synth.make_problem("2d_64x64x4")
+    x0 = P["x0"].astype(np.complex64)
+    co = synth.co_region((1, 64, 64), P["kdims"], (1, 2))
+    sched = [(co[0], co[1], 5)] * 3 + [((0, 0, 0), (1, 64, 64), 5)] * 3
+    ref = oracle.solve(x0.astype(np.complex128), P["mask"], P["kdims"], P["rank"], sched, p=8, seed=77)
+    x, tr = hc.solve(_dev(x0), _dev(P["mask"]), P["kdims"], P["rank"], sched, p=8, seed=77)
+    xh = x.cpu().numpy()
+    d = oracle.ser(xh, P["x_true"]) - oracle.ser(ref, P["x_true"])
+    print("JL+CO rel err", oracle.rel_err(xh, ref), "dSER", d, flush=True)
+    assert oracle.rel_err(xh, ref) <= 1e-3
+    assert abs(d) <= 0.02
+    # resume after the third outer iteration reproduces the uninterrupted run
+    # bit for bit (cold-started eigensolves on both sides: a warm start carries
+    # eigenvector state that a resumed run does not have)
+    kw = dict(p=8, seed=77, warm_start=False)
+    xf, _ = hc.solve(_dev(x0), _dev(P["mask"]), P["kdims"], P["rank"], sched, **kw)
+    x3, _ = hc.solve(_dev(x0), _dev(P["mask"]), P["kdims"], P["rank"], sched[:3], **kw)
+    xr, _ = hc.solve(x3, _dev(P["mask"]), P["kdims"], P["rank"], sched, start_outer=3, **kw)
+    np.testing.assert_array_equal(xr.cpu().numpy(), xf.cpu().numpy())
+
+
+def test_full_size_sampled_parity(hc):
+    """2d_256x232x16 with the 280-filter nullspace, in the launch
+    configuration the benchmark times: J against the explicit oracle, g at
+    sampled locations against the point-wise oracle."""
+    P = synth.make_problem("2d_256x232x16")
+    x = P["x0"].astype(np.complex64)
+    kd, lo, hi = P["kdims"], (0, 0, 0), (1, 256, 232)
+    xr = x.astype(np.complex128)
+    Q, _, _ = oracle.nullspace(oracle.gram(xr, kd, lo, hi), P["rank"])
+    F = Q.astype(np.complex64)
+    Fr = F.astype(np.complex128)
+    for prec in ("fp32", "bf16x3", "bf16"):
+        print("full size", prec, flush=True)
+        J, g, gn2 = hc.objective_grad(_dev(x), _dev(P["mask"]), _dev(F), kd, lo, hi, prec=prec)
+        Y, eY = forward_bound(xr, Fr, kd, lo, hi, prec)
+        Jr = float(np.vdot(Y, Y).real)
+        assert abs(J.item() - Jr) <= sumsq_bound(Y, eY)
+        gh = g.cpu().numpy()
+        rng = np.random.default_rng(0)
+        pts = [(0, int(a), int(b)) for a, b in zip(rng.integers(0, 256, 48), rng.integers(0, 232, 48))]
+        pts += [(0, 0, 0), (0, 255, 231), (0, 128, 116), (0, 2, 230)]
+        gr = oracle.grad_at_points(xr, P["mask"], Fr, kd, lo, hi, pts)
+        b = grad_bound_at_points(xr, Fr, kd, lo, hi, prec, pts)
+        for i, w in enumerate(pts):
+            if P["mask"][w]:
+                assert np.all(gh[w] == 0)
+            else:
+                assert np.all(np.abs(gh[w] - gr[i]) <= b[i]), (prec, w)
