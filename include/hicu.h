@@ -200,13 +200,37 @@ typedef struct {
   double J, gnorm2, eta;
 } hicu_trace;
 
-/* x0_dev    complex64 zero-filled observations (full array).
+/* With p = 0 the iterates depend on the nullspace only through Q Q', so
+ * the eigensolver stops resolving rotations below 1e-13 of the largest Gram
+ * diagonal entry (its own rounding level); with JL (p > 0) the individual
+ * eigenvectors matter and are resolved as in hicu_nullspace.
+ * x0_dev    complex64 zero-filled observations (full array).
  * mask_dev  uint8 observed mask (may be NULL).
  * x_out_dev complex64 result; may alias x0_dev.
  * Allocates its own device workspace for the call.  Synchronous. */
 int32_t hicu_solve(const hicu_geom* geom, const void* x0_dev, const uint8_t* mask_dev,
                    const hicu_params* params, void* x_out_dev, hicu_trace* trace_host,
                    void* stream);
+
+/* ------------------------------------------------------------------------
+ * Per-kernel timing (tracing aid, not part of the method).  Between
+ * hicu_profile_begin() and hicu_profile_end() every library launch is
+ * bracketed by HIP events recorded on its own stream.  hicu_profile_end()
+ * waits for those events and returns one record per kernel class (up to
+ * max_stats; *n_stats receives the number of classes).  flops/bytes are the
+ * algorithmic work summed over the class's launches (the convolutions count
+ * 8 n p s real flops each: one complex multiply-add per tap, filter and
+ * output).  Process-wide; not meant for concurrent use from several threads.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  char name[24];
+  int64_t launches;
+  double total_ms, min_ms, max_ms;
+  double flops, bytes;
+} hicu_kernel_stat;
+
+int32_t hicu_profile_begin(void);
+int32_t hicu_profile_end(hicu_kernel_stat* stats, int32_t max_stats, int32_t* n_stats);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,8 @@ gradient steps and exact line search on ||H(x) Q||_F^2 (Algorithm 1).
 """
 from ._lib import HicuError, load, LIB_PATH
 from .api import (geom, num_taps, gram, nullspace, jl_compress, workspace_bytes, objective_grad,
-                  line_search, update, solve)
+                  line_search, update, solve, profile_begin, profile_end)
 
 __all__ = ["HicuError", "load", "LIB_PATH", "geom", "num_taps", "gram", "nullspace", "jl_compress",
-           "workspace_bytes", "objective_grad", "line_search", "update", "solve"]
+           "workspace_bytes", "objective_grad", "line_search", "update", "solve", "profile_begin",
+           "profile_end"]

@@ -37,6 +37,12 @@ class Trace(ctypes.Structure):
                 ("J", ctypes.c_double), ("gnorm2", ctypes.c_double), ("eta", ctypes.c_double)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class HicuError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -62,6 +68,8 @@ SIGNATURES = {
     "hicu_line_search": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "hicu_update": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hicu_profile_begin": (c_int32, []),
+    "hicu_profile_end": (c_int32, [ctypes.POINTER(KernelStat), c_int32, ctypes.POINTER(c_int32)]),
     "hicu_solve": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p,
                              ctypes.POINTER(Trace), c_void_p]),
 }

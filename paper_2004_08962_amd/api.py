@@ -189,3 +189,22 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     trace = [dict(outer=t.outer, inner=t.inner, prec=t.prec, sweeps=t.sweeps, J=t.J, gnorm2=t.gnorm2, eta=t.eta)
              for t in tr[:total]]
     return x, trace
+
+
+def profile_begin():
+    """Start per-kernel event timing (every library launch, on its stream)."""
+    check(load().hicu_profile_begin(), "hicu_profile_begin")
+
+
+def profile_end(max_stats=64):
+    """Stop timing; returns {kernel class: dict(launches, total_ms, min_ms,
+    max_ms, avg_ms, flops, bytes)} with algorithmic flops/bytes summed."""
+    from ._lib import KernelStat
+    buf = (KernelStat * max_stats)()
+    n = ctypes.c_int32(0)
+    check(load().hicu_profile_end(buf, max_stats, ctypes.byref(n)), "hicu_profile_end")
+    out = {}
+    for s in buf[:min(n.value, max_stats)]:
+        out[s.name.decode()] = dict(launches=int(s.launches), total_ms=s.total_ms, min_ms=s.min_ms, max_ms=s.max_ms,
+                                    avg_ms=s.total_ms / max(1, s.launches), flops=s.flops, bytes=s.bytes)
+    return out

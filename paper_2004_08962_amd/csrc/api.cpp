@@ -13,6 +13,7 @@
 #include "eig.h"
 #include "gram.h"
 #include "ops.h"
+#include "prof.h"
 
 namespace hicu {
 
@@ -120,7 +121,19 @@ int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* s
   return HICU_OK;
 }
 
+// Profiler tag of a contraction: kind (0 forward, 1 adjoint, 2 line search) x precision.
+const char* conv_tag(int kind, int prec) {
+  static const char* tags[3][3] = {{"conv_fwd_fp32", "conv_fwd_bf16", "conv_fwd_bf16x3"},
+                                   {"conv_adj_fp32", "conv_adj_bf16", "conv_adj_bf16x3"},
+                                   {"conv_els_fp32", "conv_els_bf16", "conv_els_bf16x3"}};
+  return tags[kind][prec];
+}
+
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+int64_t region_points(const Geo& g) {
+  return (g.hi[0] - g.lo[0]) * (g.hi[1] - g.lo[1]) * (g.hi[2] - g.lo[2]);
+}
 
 bool full_region(const Geo& g) {
   for (int a = 0; a < 3; ++a)
@@ -166,15 +179,32 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   HICU_TRY(make_step_plan(g, p, prec, gout != nullptr, &sp));
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
   const float2* Fc = reinterpret_cast<const float2*>(F);
-  HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, at(ws, sp.off_Bf), at(ws, sp.off_Bflo), st));
+  const double flops = 8.0 * g.n * (double)p * (double)g.s;
+  const double nS = (double)region_points(g);
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, at(ws, sp.off_Bf), at(ws, sp.off_Bflo), st));
+  }
   float2* Y = reinterpret_cast<float2*>(at(ws, sp.off_Y));
   double* pf = reinterpret_cast<double*>(at(ws, sp.off_pf));
   fill_forward_args(g, x, sp, ws, gout ? reinterpret_cast<float*>(Y) : nullptr, pf);
-  HICU_TRY(launch_conv(sp.cf, st));
-  if (J) HICU_TRY(launch_reduce(pf, sp.nf_blocks, J, st));
+  {
+    ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * p : 0.0)));
+    HICU_TRY(launch_conv(sp.cf, st));
+  }
+  if (J) {
+    ProfScope ps("reduce", st);
+    HICU_TRY(launch_reduce(pf, sp.nf_blocks, J, st));
+  }
   if (!gout) return HICU_OK;
-  if (!full_region(g)) HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
-  HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
+  if (!full_region(g)) {
+    ProfScope ps("zero", st);
+    HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
+  }
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
+  }
   ConvArgs& a = sp.ca.a;
   a.in = Y;
   a.is[0] = g.m[1] * g.m[2] * p;
@@ -204,8 +234,14 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   a.accumulate = 0;
   double* pa = reinterpret_cast<double*>(at(ws, sp.off_pa));
   a.partial = pa;
-  HICU_TRY(launch_conv(sp.ca, st));
-  if (gn2) HICU_TRY(launch_reduce(pa, sp.na_blocks, gn2, st));
+  {
+    ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * p + nS * g.nc) + nS);
+    HICU_TRY(launch_conv(sp.ca, st));
+  }
+  if (gn2) {
+    ProfScope ps("reduce", st);
+    HICU_TRY(launch_reduce(pa, sp.na_blocks, gn2, st));
+  }
   return HICU_OK;
 }
 
@@ -216,12 +252,21 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
   // The line-search layout is a prefix-compatible subset of the gradient
   // layout only when no Y is stored, so use its own offsets.
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
-  HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
-                               at(ws, sp.off_Bflo), st));
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
+                                 at(ws, sp.off_Bflo), st));
+  }
   double* pz = reinterpret_cast<double*>(at(ws, sp.off_pz));
   fill_forward_args(g, gv, sp, ws, nullptr, pz);
-  HICU_TRY(launch_conv(sp.cf, st));
-  HICU_TRY(launch_eta(pz, sp.nf_blocks, gn2, eta, st));
+  {
+    ProfScope ps(conv_tag(2, prec), st, 8.0 * g.n * (double)p * (double)g.s, 8.0 * (double)region_points(g) * g.nc);
+    HICU_TRY(launch_conv(sp.cf, st));
+  }
+  {
+    ProfScope ps("eta", st);
+    HICU_TRY(launch_eta(pz, sp.nf_blocks, gn2, eta, st));
+  }
   return HICU_OK;
 }
 
@@ -279,6 +324,7 @@ int32_t hicu_gram(const hicu_geom* gm, const void* x, void* G, void* ws, size_t 
   Geo g;
   HICU_TRY(make_geo(gm, &g));
   if (!x || !G) return HICU_ERR_ARG;
+  ProfScope ps("gram", (hipStream_t)stream, 8.0 * (double)g.s * g.n * g.n, 8.0 * region_points(g) * g.nc);
   return launch_gram(g, x, G, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -289,12 +335,14 @@ int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G, const void* V0, v
   if (n < 1 || n > 16384) return HICU_ERR_ARG;
   if (rank < 0 || rank >= n) return HICU_ERR_RANK;
   if (!G || (!Q && !V && !evals)) return HICU_ERR_ARG;
-  return run_eig(n, rank, G, V0, Q, evals, V, sweeps, ws, ws_bytes, (hipStream_t)stream);
+  ProfScope ps("eig", (hipStream_t)stream);
+  return run_eig(n, rank, G, V0, Q, evals, V, sweeps, ws, ws_bytes, (hipStream_t)stream, false);
 }
 
 int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q, uint64_t seed, uint32_t outer,
                          uint32_t inner, uint32_t sid, void* F, double* P, void* stream) {
   if (n < 1 || nq < 1 || p < 1 || !Q || !F) return HICU_ERR_ARG;
+  ProfScope ps("jl", (hipStream_t)stream);
   return launch_jl(reinterpret_cast<const float2*>(Q), n, nq, p, seed, outer, inner, sid,
                    reinterpret_cast<float2*>(F), P, (hipStream_t)stream);
 }
@@ -329,6 +377,7 @@ int32_t hicu_update(const hicu_geom* gm, void* x, const void* gv, const double* 
   Geo g;
   HICU_TRY(make_geo(gm, &g));
   if (!x || !gv || !eta) return HICU_ERR_ARG;
+  ProfScope ps("update", (hipStream_t)stream, 0.0, 24.0 * (double)g.npts * g.nc);
   return launch_update(reinterpret_cast<float2*>(x), reinterpret_cast<const float2*>(gv), eta,
                        g.npts * g.nc, (hipStream_t)stream);
 }
@@ -401,10 +450,18 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
   std::vector<int32_t> outer_of(prec_of.size()), inner_of(prec_of.size());
   for (int i = prm->start_outer; i < prm->n_outer; ++i) {
     const Geo& gi = geos[i];
-    HICU_TRY(launch_gram(gi, x, at(ws, o_G), at(ws, o_gram), ws_gram, st));
+    {
+      ProfScope ps("gram", st, 8.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);
+      HICU_TRY(launch_gram(gi, x, at(ws, o_G), at(ws, o_gram), ws_gram, st));
+    }
     int32_t sw = 0;
-    const int32_t es = run_eig(n, r, at(ws, o_G), (prm->warm_start && have_prev) ? Vprev : nullptr, at(ws, o_Q),
-                               nullptr, Vcur, &sw, at(ws, o_eig), eig_workspace(n), st);
+    int32_t es;
+    {
+      ProfScope ps("eig", st);
+      es = run_eig(n, r, at(ws, o_G), (prm->warm_start && have_prev) ? Vprev : nullptr, at(ws, o_Q), nullptr, Vcur,
+                   &sw, at(ws, o_eig), eig_workspace(n), st,
+                   prm->p == 0);
+    }
     if (es < 0 && es != HICU_ERR_NOCONV) return es;
     if (es == HICU_ERR_NOCONV) status = HICU_ERR_NOCONV;
     sweeps_of[i] = sw;
@@ -417,6 +474,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
       inner_of[step] = j;
       const void* F = at(ws, o_Q);
       if (prm->p > 0) {
+        ProfScope ps("jl", st);
         HICU_TRY(launch_jl(reinterpret_cast<const float2*>(at(ws, o_Q)), n, nq, pf, prm->seed, (uint32_t)i,
                            (uint32_t)j, 0u, reinterpret_cast<float2*>(at(ws, o_F)), nullptr, st));
         F = at(ws, o_F);
@@ -424,6 +482,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
       double* Jd = sc + 3 * step;
       HICU_TRY(objective_grad_impl(gi, x, mask, F, pf, prec, Jd, g, Jd + 1, at(ws, o_step), ws_step, st));
       HICU_TRY(line_search_impl(gi, g, Jd + 1, F, pf, prec, Jd + 2, at(ws, o_step), ws_step, st));
+      ProfScope ps("update", st, 0.0, 24.0 * (double)N);
       HICU_TRY(launch_update(x, g, Jd + 2, (int64_t)N, st));
     }
   }

@@ -8,8 +8,9 @@
 // Hermitian subproblem with cyclic complex Jacobi rotations in LDS, and a
 // second kernel applies the block-diagonal unitary W to the whole matrix and
 // to the eigenvector accumulator (A <- W' A W, V <- V W) one 32 x 32 block per
-// workgroup, ping-ponging between two buffers.  A sweep ends with a relative
-// off-diagonal test; FP64 throughout.
+// workgroup, in place.  Pairs that are already diagonal are skipped, so
+// warm-started solves (the previous eigenvectors as V0) cost little.  A sweep
+// ends with a relative off-diagonal test; FP64 throughout.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -20,7 +21,7 @@ namespace hicu {
 
 constexpr int BS = 16;        // index block
 constexpr int SB = 2 * BS;    // subproblem size
-constexpr int MAX_INNER = 12; // inner sweeps per subproblem
+constexpr int MAX_INNER = 1;  // inner sweeps per subproblem (the outer sweeps finish the job)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -41,26 +42,12 @@ struct Rot {
   double cs, sn;
   double2 e;   // unit phase of the off-diagonal entry
   int p, q;
+  int did;     // rotation applied (otherwise identity)
 };
 
 // Rotation that diagonalises [[a, c], [conj(c), b]]: J = diag(1, conj(e)) R,
 // R = [[cs, sn], [-sn, cs]], with t = sn/cs the smaller root of
-// t^2 + 2 zeta t - 1 = 0, zeta = (b - a) / (2 |c|).
-// Entries below tol * sqrt(|a b|) or below the absolute floor (the rounding
-// level of the subproblem) are left alone.
-__device__ __forceinline__ bool make_rot(double a, double b, double2 c, double tol, double floor_abs, Rot* r) {
-  const double ac = sqrt(c.x * c.x + c.y * c.y);
-  r->cs = 1.0;
-  r->sn = 0.0;
-  r->e = make_double2(1.0, 0.0);
-  if (!(ac > tol * sqrt(fabs(a * b))) || !(ac > floor_abs)) return false;
-  const double zeta = (b - a) / (2.0 * ac);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  r->cs = 1.0 / sqrt(1.0 + t * t);
-  r->sn = t * r->cs;
-  r->e = make_double2(c.x / ac, c.y / ac);
-  return true;
-}
+// t^2 + 2 zeta t - 1 = 0, zeta = (b - a) / (2 |c|) (make_rot_fast below).
 
 // B' = Ja^H B Jb for the 2x2 block B = [[b00, b01], [b10, b11]].
 __device__ __forceinline__ void rot2x2(const Rot& ra, const Rot& rb, double2& b00, double2& b01, double2& b10,
@@ -87,146 +74,245 @@ __device__ __forceinline__ void block_indices(int r, int nb, int pair, int* idx)
   }
 }
 
-// One workgroup per block pair: full eigendecomposition of the 32x32
-// subproblem, U written to Ubuf[pair].
-__global__ __launch_bounds__(256) void pair_eig_kernel(const double2* A, int npad, int nb, int round,
-                                                       double tol, double2* Ubuf) {
-  __shared__ double2 S[SB][SB + 1];
+// Fast unitary-to-rounding rotation: reciprocal square roots and
+// reciprocals from the hardware approximations plus one Newton step each.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+
+__device__ __forceinline__ bool make_rot_fast(double a, double b, double2 c, double tol, double floor_abs, Rot* r) {
+  const double c2 = c.x * c.x + c.y * c.y;
+  r->cs = 1.0;
+  r->sn = 0.0;
+  r->e = make_double2(1.0, 0.0);
+  if (!(c2 > tol * tol * fabs(a * b)) || !(c2 > floor_abs * floor_abs)) return false;
+  const double inv = rsqrt_nr(c2);          // 1 / |c|
+  const double zeta = 0.5 * (b - a) * inv;
+  const double az = fabs(zeta);
+  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); for huge |zeta| use 1/(2 zeta)
+  const double t = az > 1e150 ? 0.5 / zeta
+                              : (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + (1.0 + zeta * zeta) * rsqrt_nr(1.0 + zeta * zeta));
+  r->cs = rsqrt_nr(1.0 + t * t);
+  r->sn = t * r->cs;
+  r->e = make_double2(c.x * inv, c.y * inv);
+  return true;
+}
+
+// One workgroup (1024 threads) per block pair: cyclic Jacobi on the 32x32
+// subproblem in LDS, U written to Ubuf[pair].  Each inner round: 16 lanes
+// compute the 16 rotations (skipping entries below the relative tolerance or
+// the absolute noise floor), then every thread produces one element of the
+// rotated S (double buffered) and one element of U.
+__global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int npad, int nb, int round,
+                                                        double tol, const double* floor_dev, double2* Ubuf,
+                                                        int* ident) {
+  __shared__ double2 S[2][SB][SB + 1];
   __shared__ double2 U[SB][SB + 1];
   __shared__ Rot rot[SB / 2];
   __shared__ int idx[SB];
-  __shared__ int nrot;
-  __shared__ double floor_abs;
+  __shared__ int nrot_round, nrot_sweep[MAX_INNER];
   const int tid = threadIdx.x;
   if (tid == 0) block_indices(round, nb, blockIdx.x, idx);
+  if (tid < MAX_INNER) nrot_sweep[tid] = 0;
   __syncthreads();
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int i = e / SB, j = e % SB;
-    S[i][j] = A[(size_t)idx[i] * npad + idx[j]];
+  {
+    const int i = tid >> 5, j = tid & 31;
+    S[0][i][j] = A[(size_t)idx[i] * npad + idx[j]];
     U[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
+  const double fl = *floor_dev;
+  // Early exit when no off-diagonal entry is above the rotation thresholds.
   __syncthreads();
-  if (tid == 0) {
-    double md = 0.0;
-    for (int i = 0; i < SB; ++i) md = fmax(md, fabs(S[i][i].x));
-    floor_abs = 4e-16 * md;
-  }
-  __syncthreads();
-  for (int sweep = 0; sweep < MAX_INNER; ++sweep) {
-    if (tid == 0) nrot = 0;
+  {
+    const int i = tid >> 5, j = tid & 31;
+    const double2 v = S[0][i][j];
+    const double v2 = v.x * v.x + v.y * v.y;
+    const bool big = i != j && v2 > fl * fl && v2 > tol * tol * fabs(S[0][i][i].x * S[0][j][j].x);
+    if (tid == 0) nrot_round = 0;
     __syncthreads();
+    if (big) nrot_round = 1;
+    __syncthreads();
+    if (nrot_round == 0) {
+      if (tid == 0) ident[blockIdx.x] = 1;
+      return;
+    }
+  }
+  // element owned by this thread: S block (al, be), entry (x, y) of the 2x2
+  const int blk = tid >> 2, al = blk >> 4, be = blk & 15, ex = (tid >> 1) & 1, ey = tid & 1;
+  // U element owned: row ui, pair ub, column (p or q) uc
+  const int ui = tid >> 5, ub = (tid >> 1) & 15, uc = tid & 1;
+  int cur = 0, total = 0;
+  for (int sweep = 0; sweep < MAX_INNER; ++sweep) {
     for (int r = 0; r < SB - 1; ++r) {
+      __syncthreads();
       if (tid < SB / 2) {
         const int p = circle_pos(tid, r, SB), q = circle_pos(SB - 1 - tid, r, SB);
         Rot ro;
-        const bool did = make_rot(S[p][p].x, S[q][q].x, S[p][q], tol, floor_abs, &ro);
+        const bool did = make_rot_fast(S[cur][p][p].x, S[cur][q][q].x, S[cur][p][q], tol, fl, &ro);
         ro.p = p;
         ro.q = q;
+        ro.did = did;
         rot[tid] = ro;
-        if (did) atomicAdd(&nrot, 1);
-      }
-      __syncthreads();
-      {
-        const Rot ra = rot[tid >> 4], rb = rot[tid & 15];
-        double2 b00 = S[ra.p][rb.p], b01 = S[ra.p][rb.q], b10 = S[ra.q][rb.p], b11 = S[ra.q][rb.q];
-        rot2x2(ra, rb, b00, b01, b10, b11);
-        if ((tid >> 4) == (tid & 15)) {
-          b01 = make_double2(0.0, 0.0);
-          b10 = make_double2(0.0, 0.0);
-          b00.y = 0.0;
-          b11.y = 0.0;
+        const uint64_t any = __ballot(did) & 0xffffull;
+        if (tid == 0) {
+          nrot_round = __popcll(any);
+          nrot_sweep[sweep] += nrot_round;
         }
-        S[ra.p][rb.p] = b00;
-        S[ra.p][rb.q] = b01;
-        S[ra.q][rb.p] = b10;
-        S[ra.q][rb.q] = b11;
-      }
-      for (int e = tid; e < SB * (SB / 2); e += 256) {
-        const int i = e / (SB / 2);
-        const Rot rb = rot[e % (SB / 2)];
-        const double2 up = U[i][rb.p], uq = U[i][rb.q];
-        const double2 eb = cconj(rb.e);
-        U[i][rb.p] = cadd(csc(rb.cs, up), csc(-rb.sn, cmul(uq, eb)));
-        U[i][rb.q] = cadd(csc(rb.sn, up), csc(rb.cs, cmul(uq, eb)));
       }
       __syncthreads();
+      if (nrot_round == 0) continue;  // uniform: nothing to rotate this round
+      const Rot ra = rot[al], rb = rot[be];
+      // Element (ex, ey) of Ja^H B Jb with B the 2x2 block of (pair al, pair be):
+      // T_j = a0 B[0][j] + a1 B[1][j], out = b0 T_0 + b1 T_1, where (a0, a1)
+      // is row ex of Ja^H and (b0, b1) column ey of Jb.
+      const double a0 = ex ? ra.sn : ra.cs;
+      const double2 a1 = ex ? csc(ra.cs, ra.e) : csc(-ra.sn, ra.e);
+      const double b0 = ey ? rb.sn : rb.cs;
+      const double2 eb = cconj(rb.e);
+      const double2 b1 = ey ? csc(rb.cs, eb) : csc(-rb.sn, eb);
+      const double2 t0 = cadd(csc(a0, S[cur][ra.p][rb.p]), cmul(a1, S[cur][ra.q][rb.p]));
+      const double2 t1 = cadd(csc(a0, S[cur][ra.p][rb.q]), cmul(a1, S[cur][ra.q][rb.q]));
+      double2 v = cadd(csc(b0, t0), cmul(t1, b1));
+      if (al == be && ra.did) {
+        if (ex != ey) v = make_double2(0.0, 0.0);
+        else v.y = 0.0;
+      }
+      const int nx = cur ^ 1;
+      S[nx][ex ? ra.q : ra.p][ey ? rb.q : rb.p] = v;
+      {
+        const Rot ru = rot[ub];
+        const double2 up = U[ui][ru.p], uq = U[ui][ru.q];
+        const double2 eu = cconj(ru.e);
+        const double c0 = uc ? ru.sn : ru.cs;
+        const double2 c1 = uc ? csc(ru.cs, eu) : csc(-ru.sn, eu);
+        const double2 w = cadd(csc(c0, up), cmul(uq, c1));
+        __syncthreads();  // every U read of this round precedes the writes
+        U[ui][uc ? ru.q : ru.p] = w;
+      }
+      cur = nx;
     }
-    if (nrot == 0) break;
     __syncthreads();
+    const int nr = nrot_sweep[sweep];
+    total += nr;
+    if (nr == 0) break;
   }
+  // A pair that needed no rotation keeps U = I; the apply step skips it.
+  if (tid == 0) ident[blockIdx.x] = total == 0;
+  if (total == 0) return;
   double2* out = Ubuf + (size_t)blockIdx.x * SB * SB;
-  for (int e = tid; e < SB * SB; e += 256) out[e] = U[e / SB][e % SB];
+  out[tid] = U[tid >> 5][tid & 31];
 }
 
-// Workgroup (alpha, beta): A'[ia, ib] = Ua^H A[ia, ib] Ub and
-// V'[ia, ib] = V[ia, ib] Ub (rows ia cover every row once over alpha).
-__global__ __launch_bounds__(256) void apply_kernel(const double2* A, double2* An, const double2* V,
-                                                    double2* Vn, int npad, int nb, int round,
-                                                    const double2* Ubuf) {
+// Workgroup (alpha, beta): A[ia, ib] <- Ua^H A[ia, ib] Ub and
+// V[ia, ib] <- V[ia, ib] Ub, in place: the (alpha, beta) blocks partition
+// both matrices, so each element is read and written by one workgroup only.
+// Pairs whose subproblem needed no rotation have U = I and are skipped.
+// 1024 threads, one output element each.  With `sums`, the workgroup also
+// writes the squared Frobenius norms of the off-diagonal part and of its
+// whole block (indices < n) for the convergence test.
+__global__ __launch_bounds__(1024) void apply_kernel(double2* A, double2* V, int n, int npad, int nb, int round,
+                                                     const double2* Ubuf, const int* ident, double* sums) {
   __shared__ double2 Bm[SB][SB + 1];
+  __shared__ double2 Vm[SB][SB + 1];
   __shared__ double2 Ua[SB][SB + 1];
   __shared__ double2 Ub[SB][SB + 1];
   __shared__ int ia[SB], ib[SB];
+  __shared__ double red[16];
   const int tid = threadIdx.x;
   const int alpha = blockIdx.x, beta = blockIdx.y;
+  const bool ida = ident[alpha] != 0, idb = ident[beta] != 0;
+  if (ida && idb && !sums) return;
   if (tid == 0) block_indices(round, nb, alpha, ia);
   if (tid == 1) block_indices(round, nb, beta, ib);
   __syncthreads();
-  const double2* ua = Ubuf + (size_t)alpha * SB * SB;
-  const double2* ub = Ubuf + (size_t)beta * SB * SB;
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int i = e / SB, j = e % SB;
-    Ua[i][j] = ua[e];
-    Ub[i][j] = ub[e];
-    Bm[i][j] = A[(size_t)ia[i] * npad + ib[j]];
+  const int r = tid >> 5, c = tid & 31;
+  const int gi = ia[r], gj = ib[c];
+  double2 out = A[(size_t)gi * npad + gj];
+  if (!(ida && idb)) {
+    const double2* ua = Ubuf + (size_t)alpha * SB * SB;
+    const double2* ub = Ubuf + (size_t)beta * SB * SB;
+    Ua[r][c] = ida ? make_double2(r == c ? 1.0 : 0.0, 0.0) : ua[tid];
+    Ub[r][c] = idb ? make_double2(r == c ? 1.0 : 0.0, 0.0) : ub[tid];
+    Bm[r][c] = out;
+    if (!idb) Vm[r][c] = V[(size_t)gi * npad + gj];
+    __syncthreads();
+    if (!ida) {  // T = Ua^H B
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+      for (int k = 0; k < SB; ++k) acc = cadd(acc, cmulc(Ua[k][r], Bm[k][c]));
+      out = acc;
+      __syncthreads();
+      Bm[r][c] = out;
+      __syncthreads();
+    }
+    if (!idb) {  // out = T Ub, V <- V Ub
+      double2 acc = make_double2(0.0, 0.0), vacc = make_double2(0.0, 0.0);
+#pragma unroll 8
+      for (int k = 0; k < SB; ++k) {
+        acc = cadd(acc, cmul(Bm[r][k], Ub[k][c]));
+        vacc = cadd(vacc, cmul(Vm[r][k], Ub[k][c]));
+      }
+      out = acc;
+      V[(size_t)gi * npad + gj] = vacc;
+    }
+    A[(size_t)gi * npad + gj] = out;
   }
-  __syncthreads();
-  const int r = tid >> 3, c0 = (tid & 7) * 4;
-  double2 t[4];
-  for (int c = 0; c < 4; ++c) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < SB; ++k) s = cadd(s, cmulc(Ua[k][r], Bm[k][c0 + c]));
-    t[c] = s;
-  }
-  __syncthreads();
-  for (int c = 0; c < 4; ++c) Bm[r][c0 + c] = t[c];
-  __syncthreads();
-  for (int c = 0; c < 4; ++c) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < SB; ++k) s = cadd(s, cmul(Bm[r][k], Ub[k][c0 + c]));
-    An[(size_t)ia[r] * npad + ib[c0 + c]] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int i = e / SB, j = e % SB;
-    Bm[i][j] = V[(size_t)ia[i] * npad + ib[j]];
-  }
-  __syncthreads();
-  for (int c = 0; c < 4; ++c) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < SB; ++k) s = cadd(s, cmul(Bm[r][k], Ub[k][c0 + c]));
-    Vn[(size_t)ia[r] * npad + ib[c0 + c]] = s;
+  if (sums) {
+    double off2 = 0.0, all2 = 0.0;
+    if (gi < n && gj < n) {
+      all2 = out.x * out.x + out.y * out.y;
+      if (gi != gj) off2 = all2;
+    }
+    off2 = block_sum_d(off2, red);
+    all2 = block_sum_d(all2, red);
+    if (tid == 0) {
+      const size_t slot = (size_t)alpha * gridDim.y + beta;
+      sums[2 * slot] = off2;
+      sums[2 * slot + 1] = all2;
+    }
   }
 }
 
-// Squared Frobenius norms of the off-diagonal part and of the whole matrix
-// (indices < n), reduced in a fixed order: out[0] = off^2, out[1] = total^2.
-__global__ __launch_bounds__(1024) void offdiag_kernel(const double2* A, int n, int npad, double* out) {
-  __shared__ double red[16];
-  double off = 0.0, tot = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    const double2 v = A[(size_t)i * npad + j];
-    const double a2 = v.x * v.x + v.y * v.y;
-    tot += a2;
-    if (i != j) off += a2;
+// Fixed-order sum of the per-block convergence partials: out = {off^2, all^2}.
+__global__ __launch_bounds__(256) void sums_kernel(const double* part, int count, double* out) {
+  __shared__ double red[4];
+  double o = 0.0, a = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    o += part[2 * i];
+    a += part[2 * i + 1];
   }
-  off = block_sum_d(off, red);
-  tot = block_sum_d(tot, red);
+  o = block_sum_d(o, red);
+  a = block_sum_d(a, red);
   if (threadIdx.x == 0) {
-    out[0] = off;
-    out[1] = tot;
+    out[0] = o;
+    out[1] = a;
   }
+}
+
+// Absolute floor of the rotations: floor_rel times the largest diagonal
+// entry of G.  With floor_rel = 2e-15 every eigenvector is resolved to
+// working accuracy; 1e-13 is the rounding level of the 32-term block updates
+// (about 32 eps times the largest eigenvalue), enough when only the
+// projector onto the nullspace matters, and it lets converged pairs be
+// skipped.
+__global__ __launch_bounds__(256) void floor_kernel(const double2* G, int n, double floor_rel, double* out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(G[(size_t)i * n + i].x));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = floor_rel * red[0];
 }
 
 // A = G padded (identity on padding), V = I or V0 padded.
@@ -317,49 +403,86 @@ __global__ void copy_vals_kernel(const double* src, double* dst, int n) {
 
 static int npad_of(int n) { return (int)rup(n, SB); }
 
-size_t eig_workspace(int n) {
-  const size_t np = (size_t)npad_of(n);
+namespace {
+struct EigLayout {
+  size_t A, V, T, U, ident, part, perm, vals, sums, total;
+};
+EigLayout eig_layout(int n) {
+  const size_t np = (size_t)npad_of(n), npair = np / SB;
   const size_t mat = np * np * sizeof(double2);
-  const size_t ub = (np / SB) * SB * SB * sizeof(double2);
-  return 4 * mat + ub + np * (sizeof(int) + sizeof(double)) + 4096;
+  EigLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) / 256 * 256;
+    return o;
+  };
+  L.A = take(mat);
+  L.V = take(mat);
+  L.T = take(mat);
+  L.U = take(npair * SB * SB * sizeof(double2));
+  L.ident = take(npair * sizeof(int));
+  L.part = take(2 * npair * npair * sizeof(double));
+  L.perm = take(np * sizeof(int));
+  L.vals = take(np * sizeof(double));
+  L.sums = take(4 * sizeof(double));
+  L.total = off;
+  return L;
 }
+}  // namespace
+
+size_t eig_workspace(int n) { return eig_layout(n).total; }
 
 int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double* evals, void* Vout,
-                int32_t* sweeps_out, void* ws, size_t ws_bytes, hipStream_t st) {
-  if (ws == nullptr || ws_bytes < eig_workspace(n)) return HICU_ERR_WORKSPACE;
-  const int np = npad_of(n), nb = np / BS;
+                int32_t* sweeps_out, void* ws, size_t ws_bytes, hipStream_t st, bool projector_only) {
+  const double floor_rel = projector_only ? 1e-13 : 2e-15;
+  const EigLayout L = eig_layout(n);
+  if (ws == nullptr || ws_bytes < L.total) return HICU_ERR_WORKSPACE;
+  const int np = npad_of(n), nb = np / BS, npair = nb / 2;
   const size_t mat = (size_t)np * np;
-  double2* A0 = reinterpret_cast<double2*>(ws);
-  double2* A1 = A0 + mat;
-  double2* Va = A1 + mat;
-  double2* Vb = Va + mat;
-  double2* Ub = Vb + mat;
-  int* perm = reinterpret_cast<int*>(Ub + (size_t)(np / SB) * SB * SB);
-  double* vals = reinterpret_cast<double*>(perm + np);
-  double* offv = vals + np;
+  char* base = reinterpret_cast<char*>(ws);
+  double2* A = reinterpret_cast<double2*>(base + L.A);
+  double2* V = reinterpret_cast<double2*>(base + L.V);
+  double2* T = reinterpret_cast<double2*>(base + L.T);
+  double2* Ub = reinterpret_cast<double2*>(base + L.U);
+  int* ident = reinterpret_cast<int*>(base + L.ident);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  int* perm = reinterpret_cast<int*>(base + L.perm);
+  double* vals = reinterpret_cast<double*>(base + L.vals);
+  double* dsums = reinterpret_cast<double*>(base + L.sums);
+  double* dfloor = dsums + 2;
   const int gblocks = (int)std::min<int64_t>(cdiv((int64_t)mat, 256), 4096);
   hipLaunchKernelGGL(init_kernel, dim3(gblocks), dim3(256), 0, st, reinterpret_cast<const double2*>(G),
-                     reinterpret_cast<const double2*>(V0), n, np, A0, Va);
+                     reinterpret_cast<const double2*>(V0), n, np, A, V);
+  hipLaunchKernelGGL(floor_kernel, dim3(1), dim3(256), 0, st, reinterpret_cast<const double2*>(G), n, floor_rel,
+                     dfloor);
   HICU_HIP_TRY(hipGetLastError());
-  double2 *A = A0, *An = A1, *V = Va, *Vn = Vb;
   if (V0) {
-    // A <- V0^H G V0 (padding stays identity since V0 is padded with I).
-    hipLaunchKernelGGL(zgemm_kernel, dim3(np / 32, np / 32), dim3(256), 0, st, V, A, An, np, 1);
-    hipLaunchKernelGGL(zgemm_kernel, dim3(np / 32, np / 32), dim3(256), 0, st, An, V, A, np, 0);
+    // A <- V0^H G V0 (the padding stays identity: V0 is padded with I).
+    hipLaunchKernelGGL(zgemm_kernel, dim3(np / 32, np / 32), dim3(256), 0, st, V, A, T, np, 1);
+    hipLaunchKernelGGL(zgemm_kernel, dim3(np / 32, np / 32), dim3(256), 0, st, T, V, A, np, 0);
     HICU_HIP_TRY(hipGetLastError());
   }
-  // Converged when the off-diagonal Frobenius norm is below 1e-13 of the
-  // whole, or when it has reached the rounding floor (below 1e-10 and no
-  // longer halving per sweep).
-  const double tol_inner = 1e-15, tol = 1e-13, tol_floor = 1e-10;
+  // A sweep visits every block pair once.  Converged when the off-diagonal
+  // Frobenius norm after a sweep is below tol of the whole, or when it has
+  // reached the rounding floor (below 1e-10 and no longer halving per sweep).
+  const double tol_inner = 1e-15, tol = projector_only ? 1e-11 : 1e-13, tol_floor = 1e-10;
   const int max_sweeps = 40;
   int sweeps = 0;
   double sums[2] = {0.0, 0.0}, prev = INFINITY;
   int32_t status = HICU_OK;
   for (;;) {
-    hipLaunchKernelGGL(offdiag_kernel, dim3(1), dim3(1024), 0, st, A, n, np, offv);
+    for (int r = 0; r < nb - 1; ++r) {
+      const bool last = r == nb - 2;
+      hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)A, np, nb, r, tol_inner,
+                         (const double*)dfloor, Ub, ident);
+      hipLaunchKernelGGL(apply_kernel, dim3(npair, npair), dim3(1024), 0, st, A, V, n, np, nb, r,
+                         (const double2*)Ub, (const int*)ident, last ? part : nullptr);
+    }
+    hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, npair * npair, dsums);
     HICU_HIP_TRY(hipGetLastError());
-    HICU_HIP_TRY(hipMemcpyAsync(sums, offv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    ++sweeps;
+    HICU_HIP_TRY(hipMemcpyAsync(sums, dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HICU_HIP_TRY(hipStreamSynchronize(st));
     const double rel = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : 0.0;
     if (!(rel == rel) || !std::isfinite(sums[1])) {
@@ -372,16 +495,6 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
       status = HICU_ERR_NOCONV;
       break;
     }
-    for (int r = 0; r < nb - 1; ++r) {
-      hipLaunchKernelGGL(pair_eig_kernel, dim3(nb / 2), dim3(256), 0, st, (const double2*)A, np, nb, r,
-                         tol_inner, Ub);
-      hipLaunchKernelGGL(apply_kernel, dim3(nb / 2, nb / 2), dim3(256), 0, st, (const double2*)A, An,
-                         (const double2*)V, Vn, np, nb, r, (const double2*)Ub);
-      std::swap(A, An);
-      std::swap(V, Vn);
-    }
-    HICU_HIP_TRY(hipGetLastError());
-    ++sweeps;
   }
   if (sweeps_out) *sweeps_out = sweeps;
   if (status == HICU_ERR_NONFINITE) return status;
