@@ -40,7 +40,12 @@ __device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typen
   }
 }
 
-template <int PREC, int T0, int T2, int WN>
+// PIPE: stage channel chunks through registers, prefetching chunk c + 1 from
+// global memory while chunk c is multiplied (used when several chunks are
+// streamed and a chunk fits in kStageSlots complex values per thread).
+constexpr int kStageSlots = 16;
+
+template <int PREC, int T0, int T2, int WN, bool PIPE>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   constexpr int KB = kblock_of(PREC);
   constexpr int NFRAG = T0 * T2;
@@ -92,30 +97,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   const int64_t npts_halo = (int64_t)a.h[0] * a.h[1] * a.h[2];
   const int64_t nstage = npts_halo * half_ps;
 
-  for (int ch = 0; ch < a.nchunks; ++ch) {
-    const int chg = a.ch0 + ch;
-    const int cbase = chg * a.chunk_c;
-    __syncthreads();
-    for (int64_t e = tid; e < nstage; e += 256) {
-      const int cs = (int)(e % half_ps);
-      const int64_t pt = e / half_ps;
-      const int hh2 = (int)(pt % a.h[2]);
-      const int64_t q = pt / a.h[2];
-      const int hh1 = (int)(q % a.h[1]);
-      const int hh0 = (int)(q / a.h[1]);
-      const int64_t i0 = a.org[0] + base0 + hh0;
-      const int64_t i1 = a.org[1] + base1 + hh1;
-      const int64_t i2 = a.org[2] + base2 + hh2;
-      const int ci = cbase + cs;
-      float2 v = make_float2(0.f, 0.f);
-      if (cs < a.chunk_c && ci < a.cin && i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] &&
-          i1 < a.vhi[1] && i2 >= a.vlo[2] && i2 < a.vhi[2])
-        v = a.in[i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + ci];
-      const int64_t off = ((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs;
-      stage_store<PREC>(lds, lds_lo, off, v);
-    }
-    __syncthreads();
-
+  auto compute_chunk = [&](const int chg) {
     for (int k0 = 0; k0 < a.k[0]; ++k0) {
       for (int k1 = 0; k1 < a.k[1]; ++k1) {
         const int shift = (k0 * a.h[1] + k1) * a.rs;
@@ -177,6 +159,92 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
             }
           }
         }
+      }
+    }
+  };
+
+  if constexpr (!PIPE) {
+    for (int ch = 0; ch < a.nchunks; ++ch) {
+      const int chg = a.ch0 + ch;
+      const int cbase = chg * a.chunk_c;
+      __syncthreads();
+      for (int64_t e = tid; e < nstage; e += 256) {
+        const int cs = (int)(e % half_ps);
+        const int64_t pt = e / half_ps;
+        const int hh2 = (int)(pt % a.h[2]);
+        const int64_t q = pt / a.h[2];
+        const int hh1 = (int)(q % a.h[1]);
+        const int hh0 = (int)(q / a.h[1]);
+        const int64_t i0 = a.org[0] + base0 + hh0;
+        const int64_t i1 = a.org[1] + base1 + hh1;
+        const int64_t i2 = a.org[2] + base2 + hh2;
+        const int ci = cbase + cs;
+        float2 v = make_float2(0.f, 0.f);
+        if (cs < a.chunk_c && ci < a.cin && i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] &&
+            i1 < a.vhi[1] && i2 >= a.vlo[2] && i2 < a.vhi[2])
+          v = a.in[i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + ci];
+        const int64_t off = ((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs;
+        stage_store<PREC>(lds, lds_lo, off, v);
+      }
+      __syncthreads();
+      compute_chunk(chg);
+    }
+  } else {
+    // Slot i of this thread stages complex value e = tid + 256 i of the
+    // chunk: its point's input offset (or -1 outside the validity box), its
+    // LDS offset and its channel slot, computed once for all chunks.
+    int64_t goff[kStageSlots];
+    int loff[kStageSlots], csl[kStageSlots];
+#pragma unroll
+    for (int i = 0; i < kStageSlots; ++i) {
+      const int64_t e = tid + 256 * i;
+      goff[i] = -2;
+      loff[i] = 0;
+      csl[i] = 0;
+      if (e < nstage) {
+        const int cs = (int)(e % half_ps);
+        const int64_t pt = e / half_ps;
+        const int hh2 = (int)(pt % a.h[2]);
+        const int64_t q = pt / a.h[2];
+        const int hh1 = (int)(q % a.h[1]);
+        const int hh0 = (int)(q / a.h[1]);
+        const int64_t i0 = a.org[0] + base0 + hh0;
+        const int64_t i1 = a.org[1] + base1 + hh1;
+        const int64_t i2 = a.org[2] + base2 + hh2;
+        const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
+                        i2 < a.vhi[2];
+        goff[i] = ok ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] : -1;
+        loff[i] = (int)(((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs);
+        csl[i] = cs;
+      }
+    }
+    float2 buf[kStageSlots];
+    auto load = [&](const int chg) {
+      const int cbase = chg * a.chunk_c;
+#pragma unroll
+      for (int i = 0; i < kStageSlots; ++i) {
+        float2 v = make_float2(0.f, 0.f);
+        if (goff[i] >= 0 && csl[i] < a.chunk_c && cbase + csl[i] < a.cin) v = a.in[goff[i] + cbase + csl[i]];
+        buf[i] = v;
+      }
+    };
+    auto store = [&]() {
+#pragma unroll
+      for (int i = 0; i < kStageSlots; ++i)
+        if (goff[i] != -2) stage_store<PREC>(lds, lds_lo, loff[i], buf[i]);
+    };
+    load(a.ch0);
+    __syncthreads();  // row tails zeroed before the first chunk lands
+    store();
+    __syncthreads();
+    for (int ch = 0; ch < a.nchunks; ++ch) {
+      const bool more = ch + 1 < a.nchunks;
+      if (more) load(a.ch0 + ch + 1);
+      compute_chunk(a.ch0 + ch);
+      if (more) {
+        __syncthreads();
+        store();
+        __syncthreads();
       }
     }
   }
@@ -375,22 +443,29 @@ int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, in
   return HICU_OK;
 }
 
-template <int PREC, int T0, int T2>
+template <int PREC, int T0, int T2, bool PIPE>
 static void launch_wn(const ConvPlan& p, hipStream_t st) {
   switch (p.t.WN) {
-    case 1: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 1>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
-    case 2: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 2>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
-    default: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 4>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
+    case 1: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 1, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
+    case 2: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 2, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
+    default: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 4, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
   }
+}
+
+template <int PREC, int T0, int T2>
+static void launch_pipe(const ConvPlan& p, hipStream_t st) {
+  const int64_t nstage = (int64_t)p.a.h[0] * p.a.h[1] * p.a.h[2] * (p.a.ps / 2);
+  if (p.a.nchunks > 1 && nstage <= 256 * kStageSlots) launch_wn<PREC, T0, T2, true>(p, st);
+  else launch_wn<PREC, T0, T2, false>(p, st);
 }
 
 template <int PREC>
 static int32_t launch_prec(const ConvPlan& p, hipStream_t st) {
   const int T0 = p.t.T0, T2 = p.t.T2;
-  if (T0 == 1 && T2 == 4) launch_wn<PREC, 1, 4>(p, st);
-  else if (T0 == 1 && T2 == 8) launch_wn<PREC, 1, 8>(p, st);
-  else if (T0 == 2 && T2 == 4) launch_wn<PREC, 2, 4>(p, st);
-  else if (T0 == 2 && T2 == 8) launch_wn<PREC, 2, 8>(p, st);
+  if (T0 == 1 && T2 == 4) launch_pipe<PREC, 1, 4>(p, st);
+  else if (T0 == 1 && T2 == 8) launch_pipe<PREC, 1, 8>(p, st);
+  else if (T0 == 2 && T2 == 4) launch_pipe<PREC, 2, 4>(p, st);
+  else if (T0 == 2 && T2 == 8) launch_pipe<PREC, 2, 8>(p, st);
   else return HICU_ERR_UNSUPPORTED;
   return HICU_OK;
 }

@@ -466,7 +466,7 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   // A sweep visits every block pair once.  Converged when the off-diagonal
   // Frobenius norm after a sweep is below tol of the whole, or when it has
   // reached the rounding floor (below 1e-10 and no longer halving per sweep).
-  const double tol_inner = 1e-15, tol = projector_only ? 1e-11 : 1e-13, tol_floor = 1e-10;
+  const double tol_inner = 1e-15, tol = projector_only ? 1e-9 : 1e-13, tol_floor = 1e-10;
   const int max_sweeps = 40;
   int sweeps = 0;
   double sums[2] = {0.0, 0.0}, prev = INFINITY;
