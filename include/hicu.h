@@ -213,6 +213,87 @@ int32_t hicu_solve(const hicu_geom* geom, const void* x0_dev, const uint8_t* mas
                    void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched gradient steps (Algorithm 1 gradient, ELS and update steps for many
+ * independent problems: slices or frames of uneven size and coil count).
+ * Every contraction of the step runs as ONE persistent launch over the work
+ * list of all (problem, tile) items; reductions are per problem in a fixed
+ * order, so each problem's result is bitwise the same as with the
+ * single-problem calls on the same tile shape.
+ *
+ * hicu_batch_item:
+ *   geom     geometry and region S of the problem
+ *   x        complex64 k-space, DEVICE, updated in place by every step
+ *   mask     uint8 observed mask or NULL
+ *   Q        complex64 n x nq nullspace basis (row-major), DEVICE
+ *   nq       columns of Q; p filters per step: p == nq uses Q itself, p < nq
+ *            draws P^(i,j) (JL, as hicu_jl_compress with stream_id = the
+ *            item's index) from the batch counter (i, j)
+ *   seed     JL seed
+ *   scalars  DEVICE double[3]: J, ||g||^2 and eta of the latest step
+ *
+ * hicu_batch_create   validates and plans (host only); *ws_bytes receives the
+ *                     device workspace size.  The handle is host memory owned
+ *                     by the library until hicu_batch_destroy.
+ * hicu_batch_bind     binds a workspace (caller-owned, >= ws_bytes), uploads
+ *                     the work tables and sets the JL counter to (0, 0);
+ *                     synchronous.
+ * hicu_batch_set_counter  sets the JL counter (i, j) with a kernel (no memset),
+ *                     so it can sit in a captured graph.
+ * hicu_batch_step     enqueues one step for every problem (kernel launches
+ *                     only; capturable); the JL inner index j is incremented
+ *                     on the device at the end of the step.
+ * hicu_batch_graph_create  captures `steps` consecutive steps into one HIP
+ *                     graph on `stream` (non-NULL); hicu_batch_graph_launch
+ *                     replays it.
+ * hicu_batch_info     info[6]: count, forward work items, adjoint work items,
+ *                     forward tile code, adjoint tile code, workspace bytes.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  hicu_geom geom;
+  void* x;
+  const uint8_t* mask;
+  const void* Q;
+  int32_t nq;
+  int32_t p;
+  uint64_t seed;
+  double* scalars;
+} hicu_batch_item;
+
+typedef struct hicu_batch_s hicu_batch;
+
+int32_t hicu_batch_create(const hicu_batch_item* items, int32_t count, int32_t prec, hicu_batch** out,
+                          size_t* ws_bytes);
+int32_t hicu_batch_bind(hicu_batch* batch, void* ws_dev, size_t ws_bytes, void* stream);
+int32_t hicu_batch_set_counter(hicu_batch* batch, uint32_t outer, uint32_t inner, void* stream);
+int32_t hicu_batch_step(hicu_batch* batch, void* stream);
+int32_t hicu_batch_graph_create(hicu_batch* batch, int32_t steps, void* stream);
+int32_t hicu_batch_graph_launch(hicu_batch* batch, void* stream);
+int32_t hicu_batch_info(const hicu_batch* batch, int64_t* info);
+void hicu_batch_destroy(hicu_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Tile-shape autotuner.  hicu_autotune times every valid tile shape of the
+ * forward and adjoint contractions on the given problem (x, F, p, prec) with
+ * HIP events and stores the fastest in a process-wide cache that every later
+ * plan with the same (contraction, precision, kernel box, coils, filters,
+ * size class) uses.  choice (optional, int32[8]): forward T0 T2 WN chunk,
+ * adjoint T0 T2 WN chunk.  Synchronous.  hicu_tune_save / hicu_tune_load
+ * write / read the cache as text (load returns the number of entries read
+ * or a negative status); hicu_tune_clear empties it.
+ * ------------------------------------------------------------------------ */
+size_t hicu_autotune_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
+int32_t hicu_autotune(const hicu_geom* geom, const void* x_dev, const void* F_dev, int32_t p, int32_t prec,
+                      void* ws_dev, size_t ws_bytes, int32_t* choice, void* stream);
+int32_t hicu_tune_save(const char* path);
+int32_t hicu_tune_load(const char* path);
+int32_t hicu_tune_clear(void);
+/* Pin the tile shape of one contraction (role 0 forward/line search, role 1
+ * adjoint; T0 in {1,2}, T2 in {4,8}, WN in {1,2,4}, chunk_c = adjoint
+ * channel chunk) for problems of this geometry, filter count and precision. */
+int32_t hicu_tune_put(const hicu_geom* geom, int32_t p, int32_t prec, int32_t role, int32_t T0, int32_t T2,
+                      int32_t WN, int32_t chunk_c);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing (tracing aid, not part of the method).  Between
  * hicu_profile_begin() and hicu_profile_end() every library launch is
  * bracketed by HIP events recorded on its own stream.  hicu_profile_end()

@@ -43,6 +43,11 @@ class KernelStat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("x", c_void_p), ("mask", c_void_p), ("Q", c_void_p), ("nq", c_int32),
+                ("p", c_int32), ("seed", c_uint64), ("scalars", c_void_p)]
+
+
 class HicuError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -70,6 +75,22 @@ SIGNATURES = {
     "hicu_update": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p]),
     "hicu_profile_begin": (c_int32, []),
     "hicu_profile_end": (c_int32, [ctypes.POINTER(KernelStat), c_int32, ctypes.POINTER(c_int32)]),
+    "hicu_batch_create": (c_int32, [ctypes.POINTER(BatchItem), c_int32, c_int32, ctypes.POINTER(c_void_p),
+                                    ctypes.POINTER(c_size_t)]),
+    "hicu_batch_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "hicu_batch_set_counter": (c_int32, [c_void_p, c_uint32, c_uint32, c_void_p]),
+    "hicu_batch_step": (c_int32, [c_void_p, c_void_p]),
+    "hicu_batch_graph_create": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "hicu_batch_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "hicu_batch_info": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "hicu_batch_destroy": (None, [c_void_p]),
+    "hicu_autotune_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),
+    "hicu_autotune": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t,
+                                ctypes.POINTER(c_int32), c_void_p]),
+    "hicu_tune_save": (c_int32, [ctypes.c_char_p]),
+    "hicu_tune_load": (c_int32, [ctypes.c_char_p]),
+    "hicu_tune_clear": (c_int32, []),
+    "hicu_tune_put": (c_int32, [ctypes.POINTER(Geom), c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "hicu_solve": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p,
                              ctypes.POINTER(Trace), c_void_p]),
 }

@@ -72,12 +72,27 @@ constexpr int kColPad = 64;  // weight columns padded to the widest tile
 
 WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total);
 
+// Arguments of the weight builder (one problem).
+struct PrepArgs {
+  const float2* F;
+  int p, nc, k0, k1, k2, mode, prec;
+  int chunk_c, ps, nkb, ncolp, KB, coutr_total;
+  int64_t total;
+  void* B;
+  void* Blo;
+};
+
 // Build weights from the filter matrix F (n x p complex64, row-major).
 //   mode 0 (forward):  input channels = coils, output columns = (filter, re/im)
 //   mode 1 (adjoint):  input channels = filters, output columns = (coil, re/im),
 //                      taps flipped and conjugated.
 int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, int p,
                             const WeightShape& ws, void* B, void* Blo, hipStream_t st);
+
+PrepArgs make_prep_args(int mode, int prec, const Geo& g, const float2* F, int p, const WeightShape& ws, void* B,
+                        void* Blo);
+// One launch building the weights of `count` problems (args in device memory).
+int32_t launch_prep_weights_batch(const PrepArgs* args_dev, int count, int64_t max_total, hipStream_t st);
 
 TileCfg default_tile(int prec, const Geo& g, int coutr);
 
@@ -87,6 +102,23 @@ int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, in
                   const int64_t oe[3], int coutr, ConvPlan* plan);
 
 int32_t launch_conv(const ConvPlan& plan, hipStream_t st);
+
+// Persistent launch over the work items of several problems that share one
+// tile shape and precision (args and tile_start in device memory).
+struct BatchConvLaunch {
+  int prec;
+  TileCfg t;
+  bool pipe;
+  const ConvArgs* args;
+  const int64_t* tile_start;
+  int nprob;
+  int64_t total;
+  unsigned grid;
+  size_t lds_bytes;
+};
+int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st);
+// Whether one channel chunk of this plan fits the register staging slots.
+bool conv_can_pipe(const ConvPlan& p);
 
 // Fixed-order sum of `count` doubles into *out (single block).
 int32_t launch_reduce(const double* part, int64_t count, double* out, hipStream_t st);

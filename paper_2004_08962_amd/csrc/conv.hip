@@ -45,8 +45,12 @@ __device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typen
 // streamed and a chunk fits in kStageSlots complex values per thread).
 constexpr int kStageSlots = 16;
 
+// One output tile: positions tile bx (of gx along the position grid) and
+// column block by.  Shared by the per-problem kernel and the persistent
+// batched kernel.
 template <int PREC, int T0, int T2, int WN, bool PIPE>
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
+__device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, const int by, const int64_t gx,
+                                          unsigned char* smem) {
   constexpr int KB = kblock_of(PREC);
   constexpr int NFRAG = T0 * T2;
   static_assert(NFRAG % 4 == 0, "tile must give each wave whole fragments");
@@ -54,18 +58,16 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   constexpr bool SPLIT = PREC == P_BF16X3;
   using E = typename LdsElem<PREC>::T;
 
-  extern __shared__ __align__(16) unsigned char smem[];
   E* lds = reinterpret_cast<E*>(smem);
   const int64_t lds_elems = (int64_t)a.h[0] * a.h[1] * a.rs;
   E* lds_lo = lds + lds_elems;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
-  const int64_t bx = blockIdx.x;
   const int64_t t2i = bx % a.nt[2];
   const int64_t t1i = (bx / a.nt[2]) % a.nt[1];
   const int64_t t0i = bx / (a.nt[2] * a.nt[1]);
   const int64_t base0 = t0i * T0, base1 = t1i * 16, base2 = t2i * T2;
-  const int n0 = a.col0 + (int)blockIdx.y * (16 * WN);
+  const int n0 = a.col0 + by * (16 * WN);
 
   // Row tails (read with zero weights) must hold finite values.
   {
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
       const int64_t ob = 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]);
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
-        const int lc = (int)blockIdx.y * (16 * WN) + j * 16 + m;
+        const int lc = by * (16 * WN) + j * 16 + m;
         if (lc >= a.coutr) continue;
         float v = masked ? 0.f : acc[f][j][i] * a.scale;
         if (a.out) {
@@ -281,65 +283,97 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
   if (a.partial) {
     __shared__ double red[4];
     const double tot = block_sum_d(ssq, red);
-    if (tid == 0) a.partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (tid == 0) a.partial[(size_t)by * gx + bx] = tot;
+  }
+}
+
+template <int PREC, int T0, int T2, int WN, bool PIPE>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  conv_tile<PREC, T0, T2, WN, PIPE>(a, blockIdx.x, blockIdx.y, gridDim.x, smem);
+}
+
+// Persistent batched launch: the work list is every (position tile, column
+// block) of every problem; tile_start[q] is the first work item of problem
+// q.  Workgroups stride over the list, so problems of any size and channel
+// count share one launch.  Each item runs the same tile code as the
+// per-problem kernel, so results are bitwise identical.
+template <int PREC, int T0, int T2, int WN, bool PIPE>
+__global__ __launch_bounds__(256) void conv_batch_kernel(const ConvArgs* args, const int64_t* tile_start, int nprob,
+                                                         int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const ConvArgs& a = args[lo];
+    const int64_t local = it - tile_start[lo];
+    const int64_t gx = a.nt[0] * a.nt[1] * a.nt[2];
+    conv_tile<PREC, T0, T2, WN, PIPE>(a, local % gx, (int)(local / gx), gx, smem);
+    __syncthreads();  // the next item reuses LDS
   }
 }
 
 // ---------------------------------------------------------------------------
 // Weight builder
 // ---------------------------------------------------------------------------
-struct PrepArgs {
-  const float2* F;
-  int p, nc, k0, k1, k2, mode, prec;
-  int chunk_c, ps, nkb, ncolp, KB, coutr_total;
-  int64_t total;
-  void* B;
-  void* Blo;
-};
+__device__ __forceinline__ void prep_element(const PrepArgs& a, const int64_t e) {
+  const int kbe = (int)(e % a.KB);
+  int64_t r = e / a.KB;
+  const int col = (int)(r % a.ncolp);
+  r /= a.ncolp;
+  const int t = (int)(r % a.nkb);
+  r /= a.nkb;
+  const int k1 = (int)(r % a.k1);
+  r /= a.k1;
+  const int k0 = (int)(r % a.k0);
+  const int ch = (int)(r / a.k0);
+  const int run = t * a.KB + kbe;
+  const int kk2 = run / a.ps, el = run % a.ps;
+  float v = 0.f;
+  if (kk2 < a.k2 && el < 2 * a.chunk_c && col < a.coutr_total) {
+    const int ci = ch * a.chunk_c + (el >> 1), ri = el & 1;
+    const int co = col >> 1, ro = col & 1;
+    if (a.mode == 0) {
+      if (ci < a.nc && co < a.p) {
+        const int64_t row = (((int64_t)k0 * a.k1 + k1) * a.k2 + kk2) * a.nc + ci;
+        const float2 f = a.F[row * a.p + co];
+        // y = x * f:  y.re = x.re f.re - x.im f.im,  y.im = x.re f.im + x.im f.re
+        v = ri == 0 ? (ro == 0 ? f.x : f.y) : (ro == 0 ? -f.y : f.x);
+      }
+    } else {
+      if (ci < a.p && co < a.nc) {
+        const int64_t row = ((((int64_t)a.k0 - 1 - k0) * a.k1 + (a.k1 - 1 - k1)) * a.k2 + (a.k2 - 1 - kk2)) * a.nc + co;
+        const float2 f = a.F[row * a.p + ci];
+        // z = y * conj(f): z.re = y.re f.re + y.im f.im,  z.im = y.im f.re - y.re f.im
+        v = ri == 0 ? (ro == 0 ? f.x : -f.y) : (ro == 0 ? f.y : f.x);
+      }
+    }
+  }
+  if (a.prec == P_F32) {
+    reinterpret_cast<float*>(a.B)[e] = v;
+  } else {
+    const uint16_t h = f2bf(v);
+    reinterpret_cast<uint16_t*>(a.B)[e] = h;
+    if (a.prec == P_BF16X3) reinterpret_cast<uint16_t*>(a.Blo)[e] = f2bf(v - bf2f(h));
+  }
+}
 
 __global__ void prep_weights_kernel(PrepArgs a) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int kbe = (int)(e % a.KB);
-    int64_t r = e / a.KB;
-    const int col = (int)(r % a.ncolp);
-    r /= a.ncolp;
-    const int t = (int)(r % a.nkb);
-    r /= a.nkb;
-    const int k1 = (int)(r % a.k1);
-    r /= a.k1;
-    const int k0 = (int)(r % a.k0);
-    const int ch = (int)(r / a.k0);
-    const int run = t * a.KB + kbe;
-    const int kk2 = run / a.ps, el = run % a.ps;
-    float v = 0.f;
-    if (kk2 < a.k2 && el < 2 * a.chunk_c && col < a.coutr_total) {
-      const int ci = ch * a.chunk_c + (el >> 1), ri = el & 1;
-      const int co = col >> 1, ro = col & 1;
-      if (a.mode == 0) {
-        if (ci < a.nc && co < a.p) {
-          const int64_t row = (((int64_t)k0 * a.k1 + k1) * a.k2 + kk2) * a.nc + ci;
-          const float2 f = a.F[row * a.p + co];
-          // y = x * f:  y.re = x.re f.re - x.im f.im,  y.im = x.re f.im + x.im f.re
-          v = ri == 0 ? (ro == 0 ? f.x : f.y) : (ro == 0 ? -f.y : f.x);
-        }
-      } else {
-        if (ci < a.p && co < a.nc) {
-          const int64_t row = ((((int64_t)a.k0 - 1 - k0) * a.k1 + (a.k1 - 1 - k1)) * a.k2 + (a.k2 - 1 - kk2)) * a.nc + co;
-          const float2 f = a.F[row * a.p + ci];
-          // z = y * conj(f): z.re = y.re f.re + y.im f.im,  z.im = y.im f.re - y.re f.im
-          v = ri == 0 ? (ro == 0 ? f.x : -f.y) : (ro == 0 ? f.y : f.x);
-        }
-      }
-    }
-    if (a.prec == P_F32) {
-      reinterpret_cast<float*>(a.B)[e] = v;
-    } else {
-      const uint16_t h = f2bf(v);
-      reinterpret_cast<uint16_t*>(a.B)[e] = h;
-      if (a.prec == P_BF16X3) reinterpret_cast<uint16_t*>(a.Blo)[e] = f2bf(v - bf2f(h));
-    }
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    prep_element(a, e);
+}
+
+// Batched weight builder: blockIdx.y selects the problem.
+__global__ void prep_weights_batch_kernel(const PrepArgs* args) {
+  const PrepArgs& a = args[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    prep_element(a, e);
 }
 
 __global__ __launch_bounds__(1024) void reduce_kernel(const double* part, int64_t count, double* out) {
@@ -365,8 +399,8 @@ WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int cou
   return w;
 }
 
-int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, int p,
-                            const WeightShape& ws, void* B, void* Blo, hipStream_t st) {
+PrepArgs make_prep_args(int mode, int prec, const Geo& g, const float2* F, int p, const WeightShape& ws, void* B,
+                        void* Blo) {
   PrepArgs a;
   a.F = F;
   a.p = p;
@@ -385,10 +419,72 @@ int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, i
   a.total = (int64_t)ws.elems;
   a.B = B;
   a.Blo = Blo;
+  return a;
+}
+
+int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, int p,
+                            const WeightShape& ws, void* B, void* Blo, hipStream_t st) {
+  const PrepArgs a = make_prep_args(mode, prec, g, F, p, ws, B, Blo);
   const int64_t blocks = std::min<int64_t>(cdiv(a.total, 256), 8192);
   hipLaunchKernelGGL(prep_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   HICU_HIP_TRY(hipGetLastError());
   return HICU_OK;
+}
+
+int32_t launch_prep_weights_batch(const PrepArgs* args_dev, int count, int64_t max_total, hipStream_t st) {
+  if (count < 1 || count > 65535) return HICU_ERR_ARG;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(max_total, 256), 2048));
+  hipLaunchKernelGGL(prep_weights_batch_kernel, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, st, args_dev);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+template <int PREC, int T0, int T2, int WN, bool PIPE>
+static void launch_batch_inst(const BatchConvLaunch& b, hipStream_t st) {
+  hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WN, PIPE>), dim3(b.grid), dim3(256), b.lds_bytes, st, b.args,
+                     b.tile_start, b.nprob, b.total);
+}
+
+template <int PREC, int T0, int T2, bool PIPE>
+static void launch_batch_wn(const BatchConvLaunch& b, hipStream_t st) {
+  switch (b.t.WN) {
+    case 1: launch_batch_inst<PREC, T0, T2, 1, PIPE>(b, st); break;
+    case 2: launch_batch_inst<PREC, T0, T2, 2, PIPE>(b, st); break;
+    default: launch_batch_inst<PREC, T0, T2, 4, PIPE>(b, st); break;
+  }
+}
+
+template <int PREC, int T0, int T2>
+static void launch_batch_pipe(const BatchConvLaunch& b, hipStream_t st) {
+  if (b.pipe) launch_batch_wn<PREC, T0, T2, true>(b, st);
+  else launch_batch_wn<PREC, T0, T2, false>(b, st);
+}
+
+template <int PREC>
+static int32_t launch_batch_prec(const BatchConvLaunch& b, hipStream_t st) {
+  const int T0 = b.t.T0, T2 = b.t.T2;
+  if (T0 == 1 && T2 == 4) launch_batch_pipe<PREC, 1, 4>(b, st);
+  else if (T0 == 1 && T2 == 8) launch_batch_pipe<PREC, 1, 8>(b, st);
+  else if (T0 == 2 && T2 == 4) launch_batch_pipe<PREC, 2, 4>(b, st);
+  else if (T0 == 2 && T2 == 8) launch_batch_pipe<PREC, 2, 8>(b, st);
+  else return HICU_ERR_UNSUPPORTED;
+  return HICU_OK;
+}
+
+int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
+  if (b.nprob < 1 || b.total < 1 || b.grid < 1) return HICU_ERR_ARG;
+  int32_t s;
+  if (b.prec == P_F32) s = launch_batch_prec<P_F32>(b, st);
+  else if (b.prec == P_BF16) s = launch_batch_prec<P_BF16>(b, st);
+  else s = launch_batch_prec<P_BF16X3>(b, st);
+  if (s != HICU_OK) return s;
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+bool conv_can_pipe(const ConvPlan& p) {
+  const int64_t nstage = (int64_t)p.a.h[0] * p.a.h[1] * p.a.h[2] * (p.a.ps / 2);
+  return nstage <= 256 * kStageSlots;
 }
 
 TileCfg default_tile(int prec, const Geo& g, int coutr) {

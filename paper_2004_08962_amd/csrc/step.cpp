@@ -1,0 +1,241 @@
+// Planning and launch sequence of one gradient step (objective, gradient,
+// exact line search) for one problem; shared by the C entry points, the
+// solver loop and the batched runtime.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ops.h"
+#include "prof.h"
+#include "step.h"
+#include "tune.h"
+
+namespace hicu {
+
+
+int32_t plan_forward(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c) {
+  *w = weight_shape(prec, g.k, g.nc, g.nc, 2 * p);
+  TuneEntry e;
+  if (tune_lookup(0, prec, g, p, &e) &&
+      plan_conv(prec, TileCfg{e.T0, e.T2, e.WN}, g.k, *w, w->nchunks, g.m, 2 * p, c) == HICU_OK)
+    return HICU_OK;
+  TileCfg t = default_tile(prec, g, 2 * p);
+  int32_t s = plan_conv(prec, t, g.k, *w, w->nchunks, g.m, 2 * p, c);
+  if (s == HICU_ERR_UNSUPPORTED && t.T0 > 1) {
+    t.T0 = 1;
+    t.T2 = 8;
+    s = plan_conv(prec, t, g.k, *w, w->nchunks, g.m, 2 * p, c);
+  }
+  return s;
+}
+
+int32_t plan_adjoint(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c) {
+  const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
+  TuneEntry e;
+  if (tune_lookup(1, prec, g, p, &e)) {
+    *w = weight_shape(prec, g.k, p, std::min(e.chunk_c, std::max(1, p)), 2 * g.nc);
+    if (plan_conv(prec, TileCfg{e.T0, e.T2, e.WN}, g.k, *w, w->nchunks, oe, 2 * g.nc, c) == HICU_OK) return HICU_OK;
+  }
+  int32_t s = HICU_ERR_UNSUPPORTED;
+  const TileCfg tiles[2] = {default_tile(prec, g, 2 * g.nc), TileCfg{1, 8, default_tile(prec, g, 2 * g.nc).WN}};
+  for (const TileCfg& t : tiles) {
+    for (int cc : {16, 8, 4}) {
+      *w = weight_shape(prec, g.k, p, std::min(cc, std::max(1, p)), 2 * g.nc);
+      s = plan_conv(prec, t, g.k, *w, w->nchunks, oe, 2 * g.nc, c);
+      if (s != HICU_ERR_UNSUPPORTED) return s;
+    }
+  }
+  return s;
+}
+
+int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* sp) {
+  HICU_TRY(plan_forward(g, p, prec, &sp->wf, &sp->cf));
+  sp->nf_blocks = (int64_t)sp->cf.grid.x * sp->cf.grid.y;
+  sp->na_blocks = 0;
+  size_t off = 0;
+  sp->off_Y = off;
+  if (need_adj) off += al((size_t)g.s * p * sizeof(float2));
+  sp->off_Bf = off;
+  off += al(sp->wf.elems * esize(prec));
+  sp->off_Bflo = off;
+  if (prec == P_BF16X3) off += al(sp->wf.elems * esize(prec));
+  sp->off_Ba = sp->off_Balo = off;
+  if (need_adj) {
+    HICU_TRY(plan_adjoint(g, p, prec, &sp->wa, &sp->ca));
+    sp->na_blocks = (int64_t)sp->ca.grid.x * sp->ca.grid.y;
+    sp->off_Ba = off;
+    off += al(sp->wa.elems * esize(prec));
+    sp->off_Balo = off;
+    if (prec == P_BF16X3) off += al(sp->wa.elems * esize(prec));
+  }
+  sp->off_pf = off;
+  off += al(sp->nf_blocks * sizeof(double));
+  sp->off_pa = off;
+  off += al(std::max<int64_t>(1, sp->na_blocks) * sizeof(double));
+  sp->off_pz = off;
+  off += al(sp->nf_blocks * sizeof(double));
+  sp->total = off;
+  return HICU_OK;
+}
+
+// Profiler tag of a contraction: kind (0 forward, 1 adjoint, 2 line search) x precision.
+const char* conv_tag(int kind, int prec) {
+  static const char* tags[3][3] = {{"conv_fwd_fp32", "conv_fwd_bf16", "conv_fwd_bf16x3"},
+                                   {"conv_adj_fp32", "conv_adj_bf16", "conv_adj_bf16x3"},
+                                   {"conv_els_fp32", "conv_els_bf16", "conv_els_bf16x3"}};
+  return tags[kind][prec];
+}
+
+
+int64_t region_points(const Geo& g) {
+  return (g.hi[0] - g.lo[0]) * (g.hi[1] - g.lo[1]) * (g.hi[2] - g.lo[2]);
+}
+
+bool full_region(const Geo& g) {
+  for (int a = 0; a < 3; ++a)
+    if (g.lo[a] != 0 || g.hi[a] != g.d[a]) return false;
+  return true;
+}
+
+void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, float* out, double* partial) {
+  ConvArgs& a = sp.cf.a;
+  a.in = reinterpret_cast<const float2*>(in);
+  a.is[0] = g.d[1] * g.d[2] * g.nc;
+  a.is[1] = g.d[2] * g.nc;
+  a.is[2] = g.nc;
+  a.cin = g.nc;
+  a.ch0 = 0;
+  for (int i = 0; i < 3; ++i) {
+    a.vlo[i] = 0;
+    a.vhi[i] = g.d[i];
+    a.org[i] = g.lo[i];
+  }
+  a.B = at(ws, sp.off_Bf);
+  a.Blo = at(ws, sp.off_Bflo);
+  a.col0 = 0;
+  a.out = out;
+  const int p = sp.cf.a.coutr / 2;
+  a.os[0] = g.m[1] * g.m[2] * p;
+  a.os[1] = g.m[2] * p;
+  a.os[2] = p;
+  a.mask = nullptr;
+  for (int i = 0; i < 3; ++i) {
+    a.ms[i] = 0;
+    a.morg[i] = 0;
+  }
+  a.scale = 1.f;
+  a.accumulate = 0;
+  a.partial = partial;
+}
+
+void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const void* Blo, void* gout,
+                       const uint8_t* mask, double* partial, ConvArgs& a) {
+  a.in = reinterpret_cast<const float2*>(Y);
+  a.is[0] = g.m[1] * g.m[2] * p;
+  a.is[1] = g.m[2] * p;
+  a.is[2] = p;
+  a.cin = p;
+  a.ch0 = 0;
+  for (int i = 0; i < 3; ++i) {
+    a.vlo[i] = 0;
+    a.vhi[i] = g.m[i];
+    a.org[i] = -(int64_t)(g.k[i] - 1);
+  }
+  a.B = B;
+  a.Blo = Blo;
+  a.col0 = 0;
+  const int64_t base = ((g.lo[0] * g.d[1] + g.lo[1]) * g.d[2] + g.lo[2]) * g.nc;
+  a.out = reinterpret_cast<float*>(reinterpret_cast<float2*>(gout) + base);
+  a.os[0] = g.d[1] * g.d[2] * g.nc;
+  a.os[1] = g.d[2] * g.nc;
+  a.os[2] = g.nc;
+  a.mask = mask;
+  a.ms[0] = g.d[1] * g.d[2];
+  a.ms[1] = g.d[2];
+  a.ms[2] = 1;
+  for (int i = 0; i < 3; ++i) a.morg[i] = g.lo[i];
+  a.scale = 2.f;
+  a.accumulate = 0;
+  a.partial = partial;
+}
+
+// Objective, gradient; shared by the public entry and the solver loop.
+int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
+                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st) {
+  StepPlan sp;
+  HICU_TRY(make_step_plan(g, p, prec, gout != nullptr, &sp));
+  if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
+  const float2* Fc = reinterpret_cast<const float2*>(F);
+  const double flops = 8.0 * g.n * (double)p * (double)g.s;
+  const double nS = (double)region_points(g);
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, at(ws, sp.off_Bf), at(ws, sp.off_Bflo), st));
+  }
+  float2* Y = reinterpret_cast<float2*>(at(ws, sp.off_Y));
+  double* pf = reinterpret_cast<double*>(at(ws, sp.off_pf));
+  fill_forward_args(g, x, sp, ws, gout ? reinterpret_cast<float*>(Y) : nullptr, pf);
+  {
+    ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * p : 0.0)));
+    HICU_TRY(launch_conv(sp.cf, st));
+  }
+  if (J) {
+    ProfScope ps("reduce", st);
+    HICU_TRY(launch_reduce(pf, sp.nf_blocks, J, st));
+  }
+  if (!gout) return HICU_OK;
+  if (!full_region(g)) {
+    ProfScope ps("zero", st);
+    HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
+  }
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
+  }
+  double* pa = reinterpret_cast<double*>(at(ws, sp.off_pa));
+  fill_adjoint_args(g, Y, p, at(ws, sp.off_Ba), at(ws, sp.off_Balo), gout, mask, pa, sp.ca.a);
+  {
+    ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * p + nS * g.nc) + nS);
+    HICU_TRY(launch_conv(sp.ca, st));
+  }
+  if (gn2) {
+    ProfScope ps("reduce", st);
+    HICU_TRY(launch_reduce(pa, sp.na_blocks, gn2, st));
+  }
+  return HICU_OK;
+}
+
+int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
+                         double* eta, void* ws, size_t ws_bytes, hipStream_t st) {
+  StepPlan sp;
+  HICU_TRY(make_step_plan(g, p, prec, false, &sp));
+  // The line-search layout is a prefix-compatible subset of the gradient
+  // layout only when no Y is stored, so use its own offsets.
+  if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
+                                 at(ws, sp.off_Bflo), st));
+  }
+  double* pz = reinterpret_cast<double*>(at(ws, sp.off_pz));
+  fill_forward_args(g, gv, sp, ws, nullptr, pz);
+  {
+    ProfScope ps(conv_tag(2, prec), st, 8.0 * g.n * (double)p * (double)g.s, 8.0 * (double)region_points(g) * g.nc);
+    HICU_TRY(launch_conv(sp.cf, st));
+  }
+  {
+    ProfScope ps("eta", st);
+    HICU_TRY(launch_eta(pz, sp.nf_blocks, gn2, eta, st));
+  }
+  return HICU_OK;
+}
+
+size_t step_workspace(const Geo& g, int p, int prec) {
+  StepPlan a, b;
+  if (make_step_plan(g, p, prec, true, &a) != HICU_OK) return 0;
+  if (make_step_plan(g, p, prec, false, &b) != HICU_OK) return 0;
+  return std::max(a.total, b.total);
+}
+
+
+}  // namespace hicu

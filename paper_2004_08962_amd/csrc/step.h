@@ -1,0 +1,46 @@
+// One gradient step of the method for one problem: forward convolution with
+// the objective, adjoint convolution with hard data matching, line-search
+// convolution (THEORY section; Algorithm 1, gradient and ELS steps).
+#pragma once
+
+#include "common.h"
+#include "conv.h"
+
+namespace hicu {
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+inline bool valid_prec(int p) { return p == P_F32 || p == P_BF16 || p == P_BF16X3; }
+inline size_t esize(int prec) { return prec == P_F32 ? 4 : 2; }
+
+// Workspace layout of one step (offsets from the workspace base).
+struct StepPlan {
+  WeightShape wf, wa;
+  ConvPlan cf, ca;      // forward (also used for the line search), adjoint
+  size_t off_Y, off_Bf, off_Bflo, off_Ba, off_Balo, off_pf, off_pa, off_pz, total;
+  int64_t nf_blocks, na_blocks;
+};
+
+int32_t plan_forward(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c);
+int32_t plan_adjoint(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c);
+int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* sp);
+const char* conv_tag(int kind, int prec);
+int64_t region_points(const Geo& g);
+bool full_region(const Geo& g);
+
+// Fill the pointer/stride/epilogue fields of sp.cf.a for H_S(in) F.
+void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, float* out, double* partial);
+
+// Fill sp.ca.a-style arguments for 2 (1 - M) o H_S'(Y F^H) written to gout.
+void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const void* Blo, void* gout,
+                       const uint8_t* mask, double* partial, ConvArgs& a);
+
+int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
+                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st);
+int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
+                         double* eta, void* ws, size_t ws_bytes, hipStream_t st);
+size_t step_workspace(const Geo& g, int p, int prec);
+
+}  // namespace hicu

@@ -1,0 +1,226 @@
+// Autotuner: times every valid tile shape of the forward and adjoint
+// contractions on the caller's problem and caches the fastest per
+// (role, precision, kernel box, coils, filters, size class).
+#include "tune.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "step.h"
+
+namespace hicu {
+namespace {
+
+std::mutex mu;
+std::map<std::string, TuneEntry> cache;
+
+std::string key_of(int role, int prec, const Geo& g, int p) {
+  char buf[160];
+  const int size_class = (int)std::floor(std::log2((double)std::max<int64_t>(1, g.s)));
+  std::snprintf(buf, sizeof(buf), "r%d/q%d/k%dx%dx%d/c%d/p%d/s%d/d%d", role, prec, g.k[0], g.k[1], g.k[2], g.nc, p,
+                size_class, g.d[0] > 1 ? 3 : 2);
+  return buf;
+}
+
+const TileCfg kTiles[] = {{1, 8, 1}, {1, 8, 2}, {1, 8, 4}, {1, 4, 1}, {1, 4, 2}, {1, 4, 4},
+                          {2, 4, 1}, {2, 4, 2}, {2, 4, 4}, {2, 8, 1}, {2, 8, 2}, {2, 8, 4}};
+
+// Median-free timing: one warm launch, then the mean of `reps` launches.
+int32_t time_plan(const ConvPlan& p, hipStream_t st, float* ms) {
+  hipEvent_t a, b;
+  HICU_HIP_TRY(hipEventCreate(&a));
+  HICU_HIP_TRY(hipEventCreate(&b));
+  int32_t s = launch_conv(p, st);
+  const int reps = 3;
+  if (s == HICU_OK) {
+    (void)hipEventRecord(a, st);
+    for (int i = 0; i < reps && s == HICU_OK; ++i) s = launch_conv(p, st);
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, a, b);
+    *ms = t / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return s;
+}
+
+}  // namespace
+
+bool tune_lookup(int role, int prec, const Geo& g, int p, TuneEntry* e) {
+  std::lock_guard<std::mutex> l(mu);
+  auto it = cache.find(key_of(role, prec, g, p));
+  if (it == cache.end()) return false;
+  *e = it->second;
+  return true;
+}
+
+void tune_store(int role, int prec, const Geo& g, int p, const TuneEntry& e) {
+  std::lock_guard<std::mutex> l(mu);
+  cache[key_of(role, prec, g, p)] = e;
+}
+
+// Workspace of the tuner: Y, a gradient buffer, the largest weight set and
+// the largest partial-sum array over the candidates.
+size_t tune_workspace(const Geo& g, int p, int prec) {
+  size_t wmax = 0;
+  for (int cc : {16, 8, 4}) wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc).elems);
+  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p).elems);
+  const int64_t ext = region_points(g);
+  const int64_t blocks = (int64_t)(cdiv(ext, 16) + 1) * 64 * cdiv(std::max(2 * p, 2 * g.nc), 16);
+  return al((size_t)g.s * p * sizeof(float2)) + al((size_t)g.npts * g.nc * sizeof(float2)) +
+         2 * al(wmax * esize(prec)) + al((size_t)blocks * sizeof(double));
+}
+
+int32_t autotune(const Geo& g, const void* x, const void* F, int p, int prec, void* ws, size_t ws_bytes,
+                 hipStream_t st, TuneEntry* best_fwd, TuneEntry* best_adj) {
+  if (ws == nullptr || ws_bytes < tune_workspace(g, p, prec)) return HICU_ERR_WORKSPACE;
+  size_t off = 0;
+  float2* Y = reinterpret_cast<float2*>(at(ws, off));
+  off += al((size_t)g.s * p * sizeof(float2));
+  float2* gbuf = reinterpret_cast<float2*>(at(ws, off));
+  off += al((size_t)g.npts * g.nc * sizeof(float2));
+  size_t wmax = 0;
+  for (int cc : {16, 8, 4}) wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc).elems);
+  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p).elems);
+  void* B = at(ws, off);
+  off += al(wmax * esize(prec));
+  void* Blo = at(ws, off);
+  off += al(wmax * esize(prec));
+  double* part = reinterpret_cast<double*>(at(ws, off));
+  const float2* Fc = reinterpret_cast<const float2*>(F);
+
+  // forward
+  StepPlan sp;
+  HICU_TRY(make_step_plan(g, p, prec, false, &sp));
+  HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, B, Blo, st));
+  TuneEntry bf{0, 0, 0, g.nc, 1e30f};
+  for (const TileCfg& t : kTiles) {
+    if (g.k[0] == 1 && t.T0 > 1) continue;  // 2-D: no second plane
+    ConvPlan cp;
+    if (plan_conv(prec, t, g.k, sp.wf, sp.wf.nchunks, g.m, 2 * p, &cp) != HICU_OK) continue;
+    sp.cf = cp;
+    fill_forward_args(g, x, sp, ws, reinterpret_cast<float*>(Y), part);
+    sp.cf.a.B = B;
+    sp.cf.a.Blo = Blo;
+    float ms = 0.f;
+    if (time_plan(sp.cf, st, &ms) != HICU_OK) continue;
+    if (ms < bf.ms) bf = TuneEntry{t.T0, t.T2, t.WN, g.nc, ms};
+  }
+  if (bf.ms >= 1e30f) return HICU_ERR_UNSUPPORTED;
+  tune_store(0, prec, g, p, bf);
+  // Y from the chosen forward, as the adjoint's input
+  HICU_TRY(make_step_plan(g, p, prec, false, &sp));
+  fill_forward_args(g, x, sp, ws, reinterpret_cast<float*>(Y), part);
+  sp.cf.a.B = B;
+  sp.cf.a.Blo = Blo;
+  HICU_TRY(launch_conv(sp.cf, st));
+
+  // adjoint
+  const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
+  TuneEntry ba{0, 0, 0, 0, 1e30f};
+  for (int cc : {16, 8, 4}) {
+    const int chunk = std::min(cc, p);
+    const WeightShape wa = weight_shape(prec, g.k, p, chunk, 2 * g.nc);
+    HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, wa, B, Blo, st));
+    for (const TileCfg& t : kTiles) {
+      if (g.k[0] == 1 && t.T0 > 1) continue;
+      ConvPlan cp;
+      if (plan_conv(prec, t, g.k, wa, wa.nchunks, oe, 2 * g.nc, &cp) != HICU_OK) continue;
+      fill_adjoint_args(g, Y, p, B, Blo, gbuf, nullptr, part, cp.a);
+      float ms = 0.f;
+      if (time_plan(cp, st, &ms) != HICU_OK) continue;
+      if (ms < ba.ms) ba = TuneEntry{t.T0, t.T2, t.WN, chunk, ms};
+    }
+    if (chunk < cc) break;
+  }
+  if (ba.ms >= 1e30f) return HICU_ERR_UNSUPPORTED;
+  tune_store(1, prec, g, p, ba);
+  if (best_fwd) *best_fwd = bf;
+  if (best_adj) *best_adj = ba;
+  HICU_HIP_TRY(hipStreamSynchronize(st));
+  return HICU_OK;
+}
+
+}  // namespace hicu
+
+using namespace hicu;
+
+extern "C" {
+
+size_t hicu_autotune_workspace_bytes(const hicu_geom* gm, int32_t p, int32_t prec) {
+  Geo g;
+  if (make_geo(gm, &g) != HICU_OK || p < 1 || !valid_prec(prec)) return 0;
+  return tune_workspace(g, p, prec);
+}
+
+int32_t hicu_autotune(const hicu_geom* gm, const void* x, const void* F, int32_t p, int32_t prec, void* ws,
+                      size_t ws_bytes, int32_t* choice, void* stream) {
+  Geo g;
+  HICU_TRY(make_geo(gm, &g));
+  if (!x || !F || !valid_prec(prec)) return HICU_ERR_ARG;
+  if (p < 1 || p > 1 << 20) return HICU_ERR_RANK;
+  TuneEntry f, a;
+  HICU_TRY(autotune(g, x, F, p, prec, ws, ws_bytes, (hipStream_t)stream, &f, &a));
+  if (choice) {
+    const int32_t c[8] = {f.T0, f.T2, f.WN, f.chunk_c, a.T0, a.T2, a.WN, a.chunk_c};
+    std::memcpy(choice, c, sizeof(c));
+  }
+  return HICU_OK;
+}
+
+int32_t hicu_tune_save(const char* path) {
+  if (!path) return HICU_ERR_ARG;
+  std::lock_guard<std::mutex> l(mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return HICU_ERR_ARG;
+  for (const auto& kv : cache)
+    std::fprintf(f, "%s %d %d %d %d %.6f\n", kv.first.c_str(), kv.second.T0, kv.second.T2, kv.second.WN,
+                 kv.second.chunk_c, kv.second.ms);
+  std::fclose(f);
+  return HICU_OK;
+}
+
+int32_t hicu_tune_load(const char* path) {
+  if (!path) return HICU_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return HICU_ERR_ARG;
+  char key[160];
+  TuneEntry e;
+  int n = 0;
+  std::lock_guard<std::mutex> l(mu);
+  while (std::fscanf(f, "%159s %d %d %d %d %f", key, &e.T0, &e.T2, &e.WN, &e.chunk_c, &e.ms) == 6) {
+    const bool ok = (e.T0 == 1 || e.T0 == 2) && (e.T2 == 4 || e.T2 == 8) && e.WN >= 1 && e.WN <= 4 &&
+                    e.WN != 3 && e.chunk_c >= 1;
+    if (ok) {
+      cache[key] = e;
+      ++n;
+    }
+  }
+  std::fclose(f);
+  return n;
+}
+
+int32_t hicu_tune_put(const hicu_geom* gm, int32_t p, int32_t prec, int32_t role, int32_t T0, int32_t T2, int32_t WN,
+                      int32_t chunk_c) {
+  Geo g;
+  HICU_TRY(make_geo(gm, &g));
+  if (!valid_prec(prec) || role < 0 || role > 1 || p < 1) return HICU_ERR_ARG;
+  if (!((T0 == 1 || T0 == 2) && (T2 == 4 || T2 == 8) && (WN == 1 || WN == 2 || WN == 4) && chunk_c >= 1))
+    return HICU_ERR_ARG;
+  tune_store(role, prec, g, p, TuneEntry{T0, T2, WN, chunk_c, 0.f});
+  return HICU_OK;
+}
+
+int32_t hicu_tune_clear(void) {
+  std::lock_guard<std::mutex> l(mu);
+  cache.clear();
+  return HICU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,21 @@
+// Tile-shape autotuner for the convolution kernels: candidates are timed on
+// the caller's problem with HIP events and the fastest is kept in a
+// process-wide cache consulted by every plan.
+#pragma once
+
+#include "common.h"
+#include "conv.h"
+
+namespace hicu {
+
+struct TuneEntry {
+  int T0, T2, WN, chunk_c;
+  float ms;
+};
+
+// role 0: forward / line-search contraction (input = k-space, output = filters)
+// role 1: adjoint contraction (input = residual, output = coils)
+bool tune_lookup(int role, int prec, const Geo& g, int p, TuneEntry* e);
+void tune_store(int role, int prec, const Geo& g, int p, const TuneEntry& e);
+
+}  // namespace hicu
