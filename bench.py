@@ -58,6 +58,35 @@ def _traffic(tag, workload, prec):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+COPY_BYTES = 256 << 20
+
+
+def summarize_traffic(paths, kernel_prefix):
+    """HBM bytes per dispatch of one kernel from two rocprofv3 --pmc runs
+    (paths = [FETCH_SIZE counter_collection.csv, WRITE_SIZE counter_collection.csv]).
+    The plain 256 MiB device copy in the same run (COPY_BYTES read and written)
+    calibrates each counter; kernel_prefix selects the kernel's dispatches by name."""
+    import csv
+    vals = {}
+    for which, path in zip(("fetch", "write"), paths):
+        rows = list(csv.DictReader(open(path)))
+        cname = "FETCH_SIZE" if which == "fetch" else "WRITE_SIZE"
+        copy, dom = [], []
+        for r in rows:
+            if r.get("Counter_Name") != cname:
+                continue
+            name = r["Kernel_Name"]
+            v = float(r["Counter_Value"])
+            if "elementwise" in name or "copy" in name.lower():
+                copy.append(v)
+            elif name.startswith(kernel_prefix):
+                dom.append(v)
+        big = max(copy)  # the 256 MiB calibration copy
+        scale = COPY_BYTES / (big * 1024.0)
+        vals[which] = (sum(dom) / len(dom) * 1024.0 * scale, scale, len(dom))
+    return vals
+
+
 def cpu_baseline(P, steps):
     """FP64 oracle on the host: one nullspace update (Gram + dense eigh) and
     `steps` gradient steps with exact line search, scaled to gradient
@@ -100,7 +129,27 @@ def main():
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--autotune", action="store_true", help="tune tile shapes on the workload before timing")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="update profiles/traffic.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--tag", default="conv_adj_bf16")
+    ap.add_argument("--prec", default="bf16")
+    ap.add_argument("--kernel", default="void hicu::conv_kernel<1, 1, 8, 2, true>",
+                    help="name prefix of the dominant kernel's dispatches in the counter CSV")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        vals = summarize_traffic(args.summarize_traffic, args.kernel)
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        db = json.load(open(path)) if os.path.exists(path) else {}
+        db["%s/%s/%s" % (args.workload, args.prec, args.tag)] = dict(
+            fetch_bytes_per_launch=vals["fetch"][0], write_bytes_per_launch=vals["write"][0],
+            fetch_scale=vals["fetch"][1], write_scale=vals["write"][1], dispatches=vals["fetch"][2],
+            kernel=args.kernel, source_sha=_sha(CONV_SOURCES))
+        json.dump(db, open(path, "w"), indent=1, sort_keys=True)
+        print(json.dumps(db[("%s/%s/%s" % (args.workload, args.prec, args.tag))]))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); see the sharding notes in the "
               "design document" % args.gpus, file=sys.stderr)
@@ -113,6 +162,12 @@ def main():
 
     hicu.load()  # fails loudly if libhicu.so is missing
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     P = synth.make_problem(args.workload)
     kd, r, sched = P["kdims"], P["rank"], P["schedule"]
     x0 = torch.from_numpy(P["x0"].astype(np.complex64)).cuda()
@@ -132,6 +187,13 @@ def main():
     def run(prec, refine):
         return hicu.solve(x0, mask, kd, r, sched, p=P["p"], seed=P["seed"], prec=prec, refine_steps=refine)
 
+    if args.autotune:
+        from paper_2004_08962_amd import batch as hb
+        G = hicu.gram(x0, kd, *sched[0][:2])
+        Q, _, _, _ = hicu.nullspace(G, r, want_V=False)
+        for prec in ("fp32", "bf16", "bf16x3"):
+            hb.autotune(x0, Q, kd, *sched[0][:2], prec=prec)
+        del G, Q
     results = {}
     for path in [q.strip() for q in args.paths.split(",") if q.strip()]:
         prec, refine = (path, 0) if path != "bf16+refine" else ("bf16", args.refine)
