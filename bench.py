@@ -59,6 +59,7 @@ def _traffic(tag, workload, prec):
 
 
 COPY_BYTES = 256 << 20
+PATHS_DEFAULT = "fp32,bf16x3,bf16+refine"
 
 
 def summarize_traffic(paths, kernel_prefix):
@@ -118,13 +119,145 @@ def cpu_baseline(P, steps):
                        "solve, %.1f s" % (steps, dt))
 
 
+def bench_gradient_steps(args, hicu, torch, np, synth):
+    """Volume workloads: a step is one gradient iteration (objective and
+    gradient, exact line search, update) over the full region with all n - r
+    nullspace filters, the nullspace taken from the device Gram and
+    eigensolver before timing.  FP32 and BF16 operand paths are timed on the
+    same inputs; the value is the BF16 path's rate."""
+    P = synth.make_problem(args.workload, dtype=np.complex64)
+    _progress("generated %s" % args.workload)
+    kd, r = P["kdims"], P["rank"]
+    dims = P["x0"].shape[:3]
+    lo, hi = (0, 0, 0), tuple(int(d) for d in dims)
+    x0 = torch.from_numpy(P["x0"]).cuda()
+    mask = torch.from_numpy(P["mask"]).cuda()
+    n = hicu.num_taps(x0.shape, kd)
+    s_out = int(np.prod([h - l - k + 1 for l, h, k in zip(lo, hi, kd)]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = hicu.gram(x0, kd, lo, hi)
+    torch.cuda.synchronize()
+    t_gram = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Q, _, _, sweeps = hicu.nullspace(G, r, want_V=False)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    del G
+    _progress("gram %.3f s, nullspace %.3f s (%d sweeps)" % (t_gram, t_eig, sweeps))
+    p = Q.shape[1]
+    precs = [q.strip() for q in args.paths.split(",") if q.strip()]
+    wsb = max(hicu.workspace_bytes(x0.shape, kd, p, q, lo, hi) for q in precs)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    results = {}
+    for prec in precs:
+        x = x0.clone()
+
+        def step():
+            J, g, gn2 = hicu.objective_grad(x, mask, Q, kd, lo, hi, prec=prec, ws=ws)
+            eta = hicu.line_search(g, gn2, Q, kd, lo, hi, prec=prec, ws=ws)
+            hicu.update(x, g, eta)
+            return J
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        hicu.profile_begin()
+        t0 = time.perf_counter()
+        Js = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = hicu.profile_end()
+        results[prec] = dict(prec=prec, seconds=dt, ms_per_step=1e3 * dt / args.steps,
+                             iters_per_s=args.steps / dt, prof=prof, J=[float(j.item()) for j in Js])
+        _progress("%s: %.1f ms per gradient iteration" % (prec, 1e3 * dt / args.steps))
+        del x
+    best = "bf16" if "bf16" in results else next(iter(results))
+    b = results[best]
+    roofline = _roofline(b, args.workload)
+    line = dict(metric=METRIC, value=round(b["iters_per_s"], 4), unit="gradient iters/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(b["ms_per_step"], 3),
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype={"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}[b["prec"]], data="synthetic",
+                config=dict(workload=args.workload, dims=list(dims), coils=int(P["x0"].shape[3]), kernel=list(kd),
+                            rank=r, filters=p, step="one gradient iteration over the full region",
+                            filter_group=hicu_filter_group(s_out, p), path=best),
+                pts_filters_per_s=round(b["iters_per_s"] * s_out * p, 1),
+                setup=dict(gram_s=round(t_gram, 3), nullspace_s=round(t_eig, 3), eig_sweeps=int(sweeps)),
+                paths={k: dict(iters_per_s=round(v["iters_per_s"], 4), ms_per_step=round(v["ms_per_step"], 3),
+                               J=v["J"], kernel_ms={kk: round(vv["total_ms"] / args.steps, 3)
+                                                    for kk, vv in v["prof"].items()})
+                       for k, v in results.items()},
+                roofline=roofline)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_volume(P, Q.cpu().numpy(), s_out)
+    print(json.dumps(line), flush=True)
+
+
+def _progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def hicu_filter_group(s, p):
+    """Filters per group under the default 16 GiB budget for Y (mirrors the library's rule)."""
+    per = s * 8
+    if p * per <= (16 << 30):
+        return p
+    return min(p, max(32, (16 << 30) // per // 32 * 32))
+
+
+def cpu_baseline_volume(P, F, s_full):
+    """FP64 oracle gradient step (objective, gradient, line search, update)
+    on a centre crop of the volume with the same filters, scaled to the full
+    region by the ratio of valid outputs (the oracle's cost is linear in s)."""
+    import numpy as np
+    import oracle
+    ncores = len(os.sched_getaffinity(0))
+    kd = P["kdims"]
+    dims = P["x0"].shape[:3]
+    crop = (12, 20, 20)
+    lo = tuple((d - c) // 2 for d, c in zip(dims, crop))
+    hi = tuple(l + c for l, c in zip(lo, crop))
+    sl = tuple(slice(l, h) for l, h in zip(lo, hi))
+    x = np.ascontiguousarray(P["x0"][sl]).astype(np.complex128)
+    m = np.ascontiguousarray(P["mask"][sl])
+    s_crop = int(np.prod([c - k + 1 for c, k in zip(crop, kd)]))
+    Fr = F.astype(np.complex128)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        oracle.descent_step(x, m, Fr, kd, (0, 0, 0), crop)
+        steps += 1
+        if time.perf_counter() - t0 > 10.0 or steps >= 20:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt * s_crop / s_full, unit="gradient iters/s", cores=ncores, kind="oracle",
+                sample="%d oracle gradient steps on a %dx%dx%d centre crop (%d valid outputs, %d filters) in "
+                       "%.1f s, scaled by %d/%d valid outputs" % (steps, crop[0], crop[1], crop[2], s_crop,
+                                                                  F.shape[1], dt, s_crop, s_full))
+
+
+def _roofline(b, workload):
+    conv = {k: v for k, v in b["prof"].items()
+            if v["flops"] > 0 and k.startswith("conv") and k.endswith("_" + b["prec"])}
+    dom = max(conv, key=lambda k: conv[k]["total_ms"])
+    d = conv[dom]
+    achieved = d["flops"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[b["prec"]]
+    return dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                frac=round(achieved / peak, 4), traffic=_traffic(dom, workload, b["prec"]),
+                kernel=dom, avg_ms=round(d["avg_ms"], 4), launches=d["launches"],
+                flops_per_launch=d["flops"] / d["launches"],
+                hbm_gbs=round(d["bytes"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e9, 1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d_256x232x16")
-    ap.add_argument("--paths", default="fp32,bf16x3,bf16+refine",
+    ap.add_argument("--paths", default=PATHS_DEFAULT,
                     help="comma list of fp32, bf16x3, bf16+refine")
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--cpu-steps", type=int, default=5)
@@ -168,6 +301,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload.startswith("3d_"):
+        if args.paths == PATHS_DEFAULT:
+            args.paths = "fp32,bf16"
+        bench_gradient_steps(args, hicu, torch, np, synth)
+        return
     P = synth.make_problem(args.workload)
     kd, r, sched = P["kdims"], P["rank"], P["schedule"]
     x0 = torch.from_numpy(P["x0"].astype(np.complex64)).cuda()
@@ -207,6 +345,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = hicu.profile_end()
+        _progress("%s: %.1f ms per solve" % (path, 1e3 * dt / args.steps))
         results[path] = dict(prec=prec, refine=refine, seconds=dt, ms_per_step=1e3 * dt / args.steps,
                              iters_per_s=args.steps * total_iters / dt, ser=ser(x), prof=prof,
                              final_J=trace[-1]["J"], sweeps=[t["sweeps"] for t in trace[::sched[0][2]]])
@@ -216,18 +355,7 @@ def main():
     best = max(ok, key=lambda k: ok[k]["iters_per_s"])
     b = results[best]
 
-    # dominant kernel of the reported path (largest share of timed kernel time)
-    conv = {k: v for k, v in b["prof"].items()
-            if v["flops"] > 0 and k.startswith("conv") and k.endswith("_" + b["prec"])}
-    dom = max(conv, key=lambda k: conv[k]["total_ms"])
-    d = conv[dom]
-    achieved = d["flops"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[b["prec"]]
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=_traffic(dom, args.workload, b["prec"]),
-                    kernel=dom, avg_ms=round(d["avg_ms"], 4), launches=d["launches"],
-                    flops_per_launch=d["flops"] / d["launches"],
-                    hbm_gbs=round(d["bytes"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e9, 1))
+    roofline = _roofline(b, args.workload)
 
     line = dict(metric=METRIC, value=round(b["iters_per_s"], 3), unit="gradient iters/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(b["ms_per_step"], 3),

@@ -153,8 +153,18 @@ int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q_dev,
  * J_dev, g_dev, gnorm2_dev  outputs; any may be NULL (g_dev NULL skips the
  *           adjoint).  J_dev/gnorm2_dev are single doubles.
  * ws_dev    at least hicu_workspace_bytes(geom, p, prec) bytes.
+ * When s x p complex values of Y exceed the filter-group budget (16 GiB by
+ * default), the filters are processed in groups (a multiple of 32 filters
+ * each): Y of one group lives in the workspace and the adjoint of each group
+ * is added into g.  J and g are the same sums taken in another order.
  * ------------------------------------------------------------------------ */
 size_t hicu_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
+
+/* Set the byte budget of Y above which the gradient groups its filters
+ * (process-wide; 0 restores the 16 GiB default).  Workspace sizes queried
+ * before a change may be too small after it (calls then return
+ * HICU_ERR_WORKSPACE).  Returns HICU_OK. */
+int32_t hicu_set_filter_group_budget(size_t bytes);
 int32_t hicu_objective_grad(const hicu_geom* geom, const void* x_dev, const uint8_t* mask_dev,
                             const void* F_dev, int32_t p, int32_t prec, double* J_dev,
                             void* g_dev, double* gnorm2_dev, void* ws_dev, size_t ws_bytes,

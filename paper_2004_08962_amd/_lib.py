@@ -68,6 +68,7 @@ SIGNATURES = {
     "hicu_jl_compress": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_uint64, c_uint32, c_uint32,
                                    c_uint32, c_void_p, c_void_p, c_void_p]),
     "hicu_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),
+    "hicu_set_filter_group_budget": (c_int32, [c_size_t]),
     "hicu_objective_grad": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "hicu_line_search": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,

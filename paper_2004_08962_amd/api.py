@@ -104,6 +104,12 @@ def jl_compress(Q, p, seed, outer, inner, stream_id=0, return_P=False):
     return (F, P) if return_P else F
 
 
+def set_filter_group_budget(nbytes):
+    """Byte budget of Y = H(x)F above which the gradient runs over filter
+    groups (0 restores the default)."""
+    check(load().hicu_set_filter_group_budget(int(nbytes)), "hicu_set_filter_group_budget")
+
+
 def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None):
     return int(load().hicu_workspace_bytes(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec)))
 

@@ -118,6 +118,11 @@ int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q, uint64
                    reinterpret_cast<float2*>(F), P, (hipStream_t)stream);
 }
 
+int32_t hicu_set_filter_group_budget(size_t bytes) {
+  set_y_budget(bytes);
+  return HICU_OK;
+}
+
 size_t hicu_workspace_bytes(const hicu_geom* gm, int32_t p, int32_t prec) {
   Geo g;
   if (make_geo(gm, &g) != HICU_OK || p < 1 || !valid_prec(prec)) return 0;

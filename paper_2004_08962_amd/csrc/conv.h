@@ -18,7 +18,8 @@ namespace hicu {
 struct ConvArgs {
   const float2* in;
   int64_t is[3];          // input strides (complex elements) per spatial axis
-  int cin;                // input complex channels (channel stride 1)
+  int cin;                // input channels are [chan_base, cin) (channel stride 1)
+  int chan_base;          // channel index stored at offset 0 of each input point
   int chunk_c;            // complex channels per LDS chunk
   int nchunks;            // chunks processed by this launch
   int ch0;                // first input chunk (and weight chunk) of this launch

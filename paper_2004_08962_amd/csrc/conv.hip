@@ -184,7 +184,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
         float2 v = make_float2(0.f, 0.f);
         if (cs < a.chunk_c && ci < a.cin && i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] &&
             i1 < a.vhi[1] && i2 >= a.vlo[2] && i2 < a.vhi[2])
-          v = a.in[i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + ci];
+          v = a.in[i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + (ci - a.chan_base)];
         const int64_t off = ((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs;
         stage_store<PREC>(lds, lds_lo, off, v);
       }
@@ -226,7 +226,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
 #pragma unroll
       for (int i = 0; i < kStageSlots; ++i) {
         float2 v = make_float2(0.f, 0.f);
-        if (goff[i] >= 0 && csl[i] < a.chunk_c && cbase + csl[i] < a.cin) v = a.in[goff[i] + cbase + csl[i]];
+        if (goff[i] >= 0 && csl[i] < a.chunk_c && cbase + csl[i] < a.cin)
+          v = a.in[goff[i] + (cbase - a.chan_base) + csl[i]];
         buf[i] = v;
       }
     };
@@ -512,6 +513,7 @@ int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, in
   plan->prec = prec;
   plan->t = t;
   a.chunk_c = ws.chunk_c;
+  a.chan_base = 0;
   a.nchunks = nchunks;
   a.ps = ws.ps;
   a.nkb = ws.nkb;
@@ -573,6 +575,7 @@ int32_t launch_conv(const ConvPlan& p, hipStream_t st) {
   if (a.ps < 2 * a.chunk_c || a.ps % 8 != 0) return HICU_ERR_SHAPE;
   if (a.rs < (p.t.T2 - 1) * a.ps + a.nkb * kblock_of(p.prec)) return HICU_ERR_SHAPE;
   if (a.nkb * kblock_of(p.prec) < a.k[2] * a.ps) return HICU_ERR_SHAPE;
+  if ((int64_t)a.ch0 * a.chunk_c < a.chan_base) return HICU_ERR_SHAPE;
   int32_t s;
   if (p.prec == P_F32) s = launch_prec<P_F32>(p, st);
   else if (p.prec == P_BF16) s = launch_prec<P_BF16>(p, st);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "ops.h"
 #include "prof.h"
@@ -48,13 +49,31 @@ int32_t plan_adjoint(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c)
   return s;
 }
 
+static std::atomic<size_t> y_budget{kYBudget};
+
+void set_y_budget(size_t bytes) { y_budget.store(bytes ? bytes : kYBudget); }
+
+int filter_group(int64_t s, int p) {
+  const size_t per = (size_t)std::max<int64_t>(s, 1) * sizeof(float2);
+  const size_t budget = y_budget.load();
+  if ((size_t)p * per <= budget) return p;
+  return (int)std::min<size_t>((size_t)p, std::max<size_t>(32, budget / per / 32 * 32));
+}
+
+// Column blocks of the forward launch restricted to filters [c0, c0 + pg).
+static unsigned group_col_blocks(const ConvPlan& c, int pg) { return (unsigned)cdiv(2 * pg, 16 * c.t.WN); }
+
 int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* sp) {
   HICU_TRY(plan_forward(g, p, prec, &sp->wf, &sp->cf));
-  sp->nf_blocks = (int64_t)sp->cf.grid.x * sp->cf.grid.y;
+  sp->pc = need_adj ? filter_group(g.s, p) : p;
+  // Forward partial sums: one per (tile, column block) of every filter group.
+  int64_t gy = 0;
+  for (int c0 = 0; c0 < p; c0 += sp->pc) gy += group_col_blocks(sp->cf, std::min(sp->pc, p - c0));
+  sp->nf_blocks = (int64_t)sp->cf.grid.x * std::max<int64_t>(gy, sp->cf.grid.y);
   sp->na_blocks = 0;
   size_t off = 0;
   sp->off_Y = off;
-  if (need_adj) off += al((size_t)g.s * p * sizeof(float2));
+  if (need_adj) off += al((size_t)g.s * sp->pc * sizeof(float2));
   sp->off_Bf = off;
   off += al(sp->wf.elems * esize(prec));
   sp->off_Bflo = off;
@@ -104,6 +123,7 @@ void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, flo
   a.is[1] = g.d[2] * g.nc;
   a.is[2] = g.nc;
   a.cin = g.nc;
+  a.chan_base = 0;
   a.ch0 = 0;
   for (int i = 0; i < 3; ++i) {
     a.vlo[i] = 0;
@@ -135,6 +155,7 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
   a.is[1] = g.m[2] * p;
   a.is[2] = p;
   a.cin = p;
+  a.chan_base = 0;
   a.ch0 = 0;
   for (int i = 0; i < 3; ++i) {
     a.vlo[i] = 0;
@@ -160,13 +181,17 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
 }
 
 // Objective, gradient; shared by the public entry and the solver loop.
+// Filters are taken in groups of sp.pc: the forward launch of a group writes
+// its columns of Y = H_S(x)F (and its share of the sum of squares), the
+// adjoint launch of the group adds H_S'(Y_group F_group^H) into g.  The sum
+// over groups is the full adjoint because H_S'(Y F^H) is linear in the
+// filter columns; the last group writes the per-block sums of |g|^2.
 int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
                             double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st) {
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, gout != nullptr, &sp));
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
   const float2* Fc = reinterpret_cast<const float2*>(F);
-  const double flops = 8.0 * g.n * (double)p * (double)g.s;
   const double nS = (double)region_points(g);
   {
     ProfScope ps("prep_weights", st);
@@ -174,31 +199,52 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   }
   float2* Y = reinterpret_cast<float2*>(at(ws, sp.off_Y));
   double* pf = reinterpret_cast<double*>(at(ws, sp.off_pf));
-  fill_forward_args(g, x, sp, ws, gout ? reinterpret_cast<float*>(Y) : nullptr, pf);
-  {
-    ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * p : 0.0)));
-    HICU_TRY(launch_conv(sp.cf, st));
-  }
-  if (J) {
-    ProfScope ps("reduce", st);
-    HICU_TRY(launch_reduce(pf, sp.nf_blocks, J, st));
-  }
-  if (!gout) return HICU_OK;
-  if (!full_region(g)) {
-    ProfScope ps("zero", st);
-    HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
-  }
-  {
+  double* pa = reinterpret_cast<double*>(at(ws, sp.off_pa));
+  if (gout) {
+    if (!full_region(g)) {
+      ProfScope ps("zero", st);
+      HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
+    }
     ProfScope ps("prep_weights", st);
     HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
   }
-  double* pa = reinterpret_cast<double*>(at(ws, sp.off_pa));
-  fill_adjoint_args(g, Y, p, at(ws, sp.off_Ba), at(ws, sp.off_Balo), gout, mask, pa, sp.ca.a);
-  {
-    ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * p + nS * g.nc) + nS);
-    HICU_TRY(launch_conv(sp.ca, st));
+  int64_t pf_used = 0;
+  for (int c0 = 0; c0 < p; c0 += sp.pc) {
+    const int pg = std::min(sp.pc, p - c0);
+    const bool last = c0 + pg == p;
+    const double flops = 8.0 * g.n * (double)pg * (double)g.s;
+    ConvPlan cf = sp.cf;
+    fill_forward_args(g, x, sp, ws, gout ? reinterpret_cast<float*>(Y) : nullptr, pf + pf_used);
+    cf.a = sp.cf.a;
+    cf.a.col0 = 2 * c0;
+    cf.a.coutr = 2 * pg;
+    cf.grid.y = group_col_blocks(cf, pg);
+    cf.a.os[0] = g.m[1] * g.m[2] * pg;
+    cf.a.os[1] = g.m[2] * pg;
+    cf.a.os[2] = pg;
+    pf_used += (int64_t)cf.grid.x * cf.grid.y;
+    {
+      ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * pg : 0.0)));
+      HICU_TRY(launch_conv(cf, st));
+    }
+    if (!gout) continue;
+    ConvPlan ca = sp.ca;
+    fill_adjoint_args(g, Y, pg, at(ws, sp.off_Ba), at(ws, sp.off_Balo), gout, mask, last ? pa : nullptr, ca.a);
+    ca.a.cin = c0 + pg;
+    ca.a.chan_base = c0;
+    ca.a.ch0 = c0 / ca.a.chunk_c;
+    ca.a.nchunks = (int)cdiv(pg, ca.a.chunk_c);
+    ca.a.accumulate = c0 > 0;
+    {
+      ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * pg + nS * g.nc * (c0 > 0 ? 2 : 1)) + nS);
+      HICU_TRY(launch_conv(ca, st));
+    }
   }
-  if (gn2) {
+  if (J) {
+    ProfScope ps("reduce", st);
+    HICU_TRY(launch_reduce(pf, pf_used, J, st));
+  }
+  if (gout && gn2) {
     ProfScope ps("reduce", st);
     HICU_TRY(launch_reduce(pa, sp.na_blocks, gn2, st));
   }

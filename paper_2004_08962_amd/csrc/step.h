@@ -15,10 +15,23 @@ inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 inline bool valid_prec(int p) { return p == P_F32 || p == P_BF16 || p == P_BF16X3; }
 inline size_t esize(int prec) { return prec == P_F32 ? 4 : 2; }
 
+// Bytes of H_S(x)F kept in device memory at once: above this the gradient
+// runs over groups of filters (forward into Y, adjoint accumulated into g),
+// since Y = s x p complex values (200 MB per filter for a 256x320x320 volume
+// with a 5x5x5 kernel) does not fit for hundreds of filters.
+constexpr size_t kYBudget = size_t(16) << 30;
+
+// Filters per group for s valid outputs and p filters: all of them when Y
+// fits the budget, else the largest multiple of 32 that does (at least 32).
+int filter_group(int64_t s, int p);
+// Replace the budget (0 restores kYBudget); process-wide.
+void set_y_budget(size_t bytes);
+
 // Workspace layout of one step (offsets from the workspace base).
 struct StepPlan {
   WeightShape wf, wa;
-  ConvPlan cf, ca;      // forward (also used for the line search), adjoint
+  ConvPlan cf, ca;      // forward over all filters (also the line search), adjoint
+  int pc;               // filters per group of the gradient
   size_t off_Y, off_Bf, off_Bflo, off_Ba, off_Balo, off_pf, off_pa, off_pz, total;
   int64_t nf_blocks, na_blocks;
 };

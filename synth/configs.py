@@ -50,7 +50,10 @@ WORKLOADS = {
     # 3-D knee-like volume 256x320x320 x 8 coils, 5x5x5 kernel, 900 nullspace filters.
     "3d_256x320x320x8": dict(dims=(256, 320, 320), nc=8, kdims=(5, 5, 5), rank=100, p=0,
                              outer=11, inner=5, last_inner=20, co_outer=10,
-                             co_axes=(0, 1, 2), seed=5),
+                             co_axes=(0, 1, 2), seed=5, centre=24),
+    # the same generator on a 16x28x28 volume (oracle-sized 3-D parity case)
+    "3d_16x28x28x8": dict(dims=(16, 28, 28), nc=8, kdims=(5, 5, 5), rank=100, p=0,
+                          outer=2, inner=3, seed=6, centre=8),
 }
 
 
@@ -102,13 +105,13 @@ def make_problem(name, dtype=np.complex128):
         maps = gaussian_coil_maps((nx, ny), nc, rng)
         x = np.stack([to_kspace(imgs[t], maps) for t in range(nt)])
         mask = cine_line_masks(nt, nx, ny, 6.0, 8, rng)
-    elif name == "3d_256x320x320x8":
+    elif name.startswith("3d_"):
         vol = ellipsoid_volume(dims, 8, rng)
         maps = gaussian_coil_maps(dims, nc, rng).astype(np.complex64)
         x = np.empty(dims + (nc,), np.complex64)
         for c in range(nc):
             x[..., c] = np.fft.fftshift(np.fft.fftn(np.fft.ifftshift(vol * maps[..., c]), norm="ortho"))
-        plane = poisson_disc_2d(dims[1], dims[2], 5.0, 24, rng)
+        plane = poisson_disc_2d(dims[1], dims[2], 5.0, w["centre"], rng)
         mask = volume_mask_from_plane(dims[0], plane)
     else:
         raise KeyError(name)

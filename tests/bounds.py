@@ -32,9 +32,10 @@ def forward_bound(x, F, kd, lo, hi, prec):
     return Y, _ops_factor(prec, 2 * n + 2) * Yabs
 
 
-def grad_bound(x, mask, F, kd, lo, hi, prec):
+def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1):
     """Elementwise bound on |g_gpu - g| for g = 2 (1-M) o H'(Y F^H), with the
-    propagated error of the stored Y (rounded to FP32) included."""
+    propagated error of the stored Y (rounded to FP32) included.  An adjoint
+    summed over `groups` filter groups adds one FP32 rounding per group."""
     p = F.shape[1]
     K = kd[0] * kd[1] * kd[2]
     Y, eY = forward_bound(x, F, kd, lo, hi, prec)
@@ -43,7 +44,7 @@ def grad_bound(x, mask, F, kd, lo, hi, prec):
     shape = x.shape
     prop = 2.0 * oracle.hankel_adjoint(eY @ Fa.T, shape, kd, lo, hi).real
     mag = 2.0 * oracle.hankel_adjoint(np.abs(Y) @ Fa.T, shape, kd, lo, hi).real
-    b = prop + _ops_factor(prec, 2 * K * p + 2) * mag
+    b = prop + _ops_factor(prec, 2 * K * p + 2 + groups) * mag
     if mask is not None:
         b[np.asarray(mask).astype(bool)] = 0.0
     return b
@@ -54,7 +55,7 @@ def sumsq_bound(v, ev):
     return float(np.sum(2.0 * np.abs(v) * ev + ev * ev)) + 1e-12 * float(np.sum(np.abs(v) ** 2))
 
 
-def grad_bound_at_points(x, F, kd, lo, hi, prec, points):
+def grad_bound_at_points(x, F, kd, lo, hi, prec, points, groups=1):
     """grad_bound evaluated only at k-space locations ``points`` (mask not
     applied), from the point-wise oracle routines on absolute values."""
     p = F.shape[1]
@@ -64,7 +65,7 @@ def grad_bound_at_points(x, F, kd, lo, hi, prec, points):
     Fa = np.abs(F)
     xa = np.abs(x)
     f1 = _ops_factor(prec, 2 * n + 2)
-    f2 = _ops_factor(prec, 2 * K * p + 2)
+    f2 = _ops_factor(prec, 2 * K * p + 2 + groups)
     out = np.zeros((len(points), nc))
     for idx, w in enumerate(points):
         acc_mag = np.zeros(nc)
