@@ -154,7 +154,7 @@ int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q_dev,
  *           adjoint).  J_dev/gnorm2_dev are single doubles.
  * ws_dev    at least hicu_workspace_bytes(geom, p, prec) bytes.
  * When s x p complex values of Y exceed the filter-group budget (16 GiB by
- * default), the filters are processed in groups (a multiple of 32 filters
+ * default), the filters are processed in groups (a multiple of 64 filters
  * each): Y of one group lives in the workspace and the adjoint of each group
  * is added into g.  J and g are the same sums taken in another order.
  * ------------------------------------------------------------------------ */
@@ -286,8 +286,8 @@ void hicu_batch_destroy(hicu_batch* batch);
  * forward and adjoint contractions on the given problem (x, F, p, prec) with
  * HIP events and stores the fastest in a process-wide cache that every later
  * plan with the same (contraction, precision, kernel box, coils, filters,
- * size class) uses.  choice (optional, int32[8]): forward T0 T2 WN chunk,
- * adjoint T0 T2 WN chunk.  Synchronous.  hicu_tune_save / hicu_tune_load
+ * size class) uses.  choice (optional, int32[4]): forward shape id and
+ * channel chunk, adjoint shape id and channel chunk.  Synchronous.  hicu_tune_save / hicu_tune_load
  * write / read the cache as text (load returns the number of entries read
  * or a negative status); hicu_tune_clear empties it.
  * ------------------------------------------------------------------------ */
@@ -298,10 +298,19 @@ int32_t hicu_tune_save(const char* path);
 int32_t hicu_tune_load(const char* path);
 int32_t hicu_tune_clear(void);
 /* Pin the tile shape of one contraction (role 0 forward/line search, role 1
- * adjoint; T0 in {1,2}, T2 in {4,8}, WN in {1,2,4}, chunk_c = adjoint
- * channel chunk) for problems of this geometry, filter count and precision. */
-int32_t hicu_tune_put(const hicu_geom* geom, int32_t p, int32_t prec, int32_t role, int32_t T0, int32_t T2,
-                      int32_t WN, int32_t chunk_c);
+ * adjoint; tile = shape id < hicu_tile_count(), a packing shape (D > 1)
+ * only for role 1; chunk_c = adjoint channel chunk) for problems of this
+ * geometry, filter count and precision. */
+int32_t hicu_tune_put(const hicu_geom* geom, int32_t p, int32_t prec, int32_t role, int32_t tile,
+                      int32_t chunk_c);
+
+/* The contraction kernels' tile shapes.  Shape `tile` covers T0 x 16 x
+ * (T2 * D) output positions and 16 * WC * FN launch columns per workgroup
+ * of four waves (wave grid (4 / WC) x WC; each wave an FM x FN grid of
+ * 16 x 16 MFMA tiles); D > 1 packs D neighbouring outputs along the last
+ * axis into the columns.  cfg receives int32[5] = {T0, T2, WC, FN, D}. */
+int32_t hicu_tile_count(void);
+int32_t hicu_tile_info(int32_t tile, int32_t* cfg);
 
 /* ------------------------------------------------------------------------
  * Per-kernel timing (tracing aid, not part of the method).  Between

@@ -91,7 +91,9 @@ SIGNATURES = {
     "hicu_tune_save": (c_int32, [ctypes.c_char_p]),
     "hicu_tune_load": (c_int32, [ctypes.c_char_p]),
     "hicu_tune_clear": (c_int32, []),
-    "hicu_tune_put": (c_int32, [ctypes.POINTER(Geom), c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "hicu_tune_put": (c_int32, [ctypes.POINTER(Geom), c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "hicu_tile_count": (c_int32, []),
+    "hicu_tile_info": (c_int32, [c_int32, c_void_p]),
     "hicu_solve": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p,
                              ctypes.POINTER(Trace), c_void_p]),
 }

@@ -80,7 +80,7 @@ class Batch:
 
 def autotune(x, F, kdims, lo=None, hi=None, prec="fp32"):
     """Time every tile shape on this problem; returns the chosen
-    (forward T0, T2, WN, chunk, adjoint T0, T2, WN, chunk)."""
+    (forward shape id, forward chunk, adjoint shape id, adjoint chunk)."""
     lib = load()
     _dev(x, torch.complex64, "x")
     _dev(F, torch.complex64, "F")
@@ -88,15 +88,27 @@ def autotune(x, F, kdims, lo=None, hi=None, prec="fp32"):
     p = F.shape[1]
     wsb = lib.hicu_autotune_workspace_bytes(ctypes.byref(g), p, _prec(prec))
     ws = _workspace(wsb, x.device)
-    choice = (ctypes.c_int32 * 8)()
+    choice = (ctypes.c_int32 * 4)()
     check(lib.hicu_autotune(ctypes.byref(g), _ptr(x), _ptr(F), p, _prec(prec), _ptr(ws), ws.numel(), choice,
                             _stream()), "hicu_autotune")
     return tuple(choice)
 
 
-def tune_put(shape, kdims, p, prec, role, T0, T2, WN, chunk, lo=None, hi=None):
-    check(load().hicu_tune_put(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec), int(role), T0, T2, WN,
-                               chunk), "hicu_tune_put")
+def tune_put(shape, kdims, p, prec, role, tile, chunk, lo=None, hi=None):
+    """Pin shape id `tile` (and adjoint channel chunk) for one contraction."""
+    check(load().hicu_tune_put(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec), int(role), int(tile),
+                               int(chunk)), "hicu_tune_put")
+
+
+def tile_info(tile):
+    """(T0, T2, WC, FN, D) of shape id `tile`."""
+    cfg = (ctypes.c_int32 * 5)()
+    check(load().hicu_tile_info(int(tile), cfg), "hicu_tile_info")
+    return tuple(cfg)
+
+
+def tile_count():
+    return int(load().hicu_tile_count())
 
 
 def tune_clear():

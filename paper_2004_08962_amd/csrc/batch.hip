@@ -159,7 +159,7 @@ struct hicu_batch_s {
   int count = 0, prec = 0;
   std::vector<hicu_batch_item> items;
   std::vector<hicu::BatchProblem> probs;
-  hicu::TileCfg tf{1, 8, 4}, ta{1, 8, 2};
+  int tf = 2, ta = 1;  // shape ids (batched shapes of the conv.h list)
   bool pipe_f = false, pipe_a = false;
   size_t lds_f = 0, lds_a = 0;
   int64_t total_f = 0, total_a = 0, max_prep_f = 0, max_prep_a = 0, max_n = 0, max_N = 0;
@@ -189,7 +189,7 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
   b->items.assign(items, items + count);
   b->probs.resize(count);
   // common tile shapes: the widest column block any problem needs, 2-D or 3-D
-  int wf = 1, wa = 1;
+  int ff = 1, fa = 1;
   bool any3d = false;
   for (int q = 0; q < count; ++q) {
     BatchProblem& P = b->probs[q];
@@ -200,12 +200,17 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     P.p = items[q].p;
     P.nq = items[q].nq;
     P.jl = P.p < P.nq;
-    wf = std::max(wf, default_tile(prec, P.g, 2 * P.p).WN);
-    wa = std::max(wa, default_tile(prec, P.g, 2 * P.g.nc).WN);
+    ff = std::max<int>(ff, (int)cdiv(2 * P.p, 16));
+    fa = std::max<int>(fa, (int)cdiv(2 * P.g.nc, 16));
     any3d = any3d || P.g.k[0] > 1;
   }
-  b->tf = any3d ? TileCfg{2, 4, wf} : TileCfg{1, 8, wf};
-  b->ta = any3d ? TileCfg{2, 4, wa} : TileCfg{1, 8, wa};
+  // batched shapes: ids 0-2 (1 x 16 x 8) and 13-15 (2 x 16 x 4) with FN = 1, 2, 4
+  auto pick = [&](int frags) {
+    const int fn = frags >= 3 ? 2 : frags - 1;
+    return any3d ? 13 + fn : fn;
+  };
+  b->tf = pick(ff);
+  b->ta = pick(fa);
   size_t off = 0;
   b->pipe_f = true;
   b->pipe_a = true;
@@ -213,19 +218,19 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     BatchProblem& P = b->probs[q];
     const Geo& g = P.g;
     StepPlan& sp = P.sp;
-    sp.wf = weight_shape(prec, g.k, g.nc, g.nc, 2 * P.p);
+    sp.wf = weight_shape(prec, g.k, g.nc, g.nc, 2 * P.p, 1);
     int32_t s = plan_conv(prec, b->tf, g.k, sp.wf, sp.wf.nchunks, g.m, 2 * P.p, &sp.cf);
     if (s != HICU_OK) return s;
     const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
     s = HICU_ERR_UNSUPPORTED;
     for (int cc : {16, 8, 4}) {
-      sp.wa = weight_shape(prec, g.k, P.p, std::min(cc, P.p), 2 * g.nc);
+      sp.wa = weight_shape(prec, g.k, P.p, std::min(cc, P.p), 2 * g.nc, 1);
       s = plan_conv(prec, b->ta, g.k, sp.wa, sp.wa.nchunks, oe, 2 * g.nc, &sp.ca);
       if (s != HICU_ERR_UNSUPPORTED) break;
     }
     if (s != HICU_OK) return s;
-    sp.nf_blocks = (int64_t)sp.cf.grid.x * sp.cf.grid.y;
-    sp.na_blocks = (int64_t)sp.ca.grid.x * sp.ca.grid.y;
+    sp.nf_blocks = sp.cf.gx * sp.cf.gy;
+    sp.na_blocks = sp.ca.gx * sp.ca.gy;
     b->pipe_f = b->pipe_f && conv_can_pipe(sp.cf);
     b->pipe_a = b->pipe_a && conv_can_pipe(sp.ca);
     b->lds_f = std::max(b->lds_f, sp.cf.lds_bytes);
@@ -298,13 +303,16 @@ int32_t batch_bind(hicu_batch_s* b, void* ws, hipStream_t st) {
     fill_forward_args(g, it.x, sp, ws, reinterpret_cast<float*>(at(ws, P.off_Y)),
                       reinterpret_cast<double*>(at(ws, P.off_pf)));
     cf[q] = sp.cf.a;
+    cf[q].vec = conv_vec(cf[q]);
     // line search: g -> (no output), partials pz
     fill_forward_args(g, gq, sp, ws, nullptr, reinterpret_cast<double*>(at(ws, P.off_pz)));
     cz[q] = sp.cf.a;
+    cz[q].vec = conv_vec(cz[q]);
     // adjoint: Y -> g, partials pa
     fill_adjoint_args(g, at(ws, P.off_Y), P.p, at(ws, P.off_Ba), at(ws, P.off_Balo), gq, it.mask,
                       reinterpret_cast<double*>(at(ws, P.off_pa)), sp.ca.a);
     ca[q] = sp.ca.a;
+    ca[q].vec = conv_vec(ca[q]);
     sf[q + 1] = sf[q] + sp.nf_blocks;
     sa[q + 1] = sa[q] + sp.na_blocks;
     pf[q] = make_prep_args(0, prec, g, F, P.p, sp.wf, at(ws, P.off_Bf), at(ws, P.off_Bflo));
@@ -479,8 +487,8 @@ int32_t hicu_batch_info(const hicu_batch* b, int64_t* info) {
   info[0] = b->count;
   info[1] = b->total_f;
   info[2] = b->total_a;
-  info[3] = b->tf.T0 * 100 + b->tf.T2 * 10 + b->tf.WN;
-  info[4] = b->ta.T0 * 100 + b->ta.T2 * 10 + b->ta.WN;
+  info[3] = b->tf;
+  info[4] = b->ta;
   info[5] = (int64_t)b->total_bytes;
   return HICU_OK;
 }

@@ -20,6 +20,7 @@ struct ConvArgs {
   int64_t is[3];          // input strides (complex elements) per spatial axis
   int cin;                // input channels are [chan_base, cin) (channel stride 1)
   int chan_base;          // channel index stored at offset 0 of each input point
+  int vec;                // channels per staged unit (4, 2 or 1; see conv_vec)
   int chunk_c;            // complex channels per LDS chunk
   int nchunks;            // chunks processed by this launch
   int ch0;                // first input chunk (and weight chunk) of this launch
@@ -47,37 +48,83 @@ struct ConvArgs {
   double* partial;        // per-block sum of squares, may be null
 };
 
-// Tile shape: T0 positions along axis 0, 16 along axis 1, T2 along axis 2
-// (T0*T2 must be a multiple of 4: one or more 16-position MFMA row fragments
-// per wave), WN 16-column fragments per wave.
+// Tile shapes.  A block of 4 waves owns T0 positions along axis 0, 16
+// along axis 1 and T2*D along axis 2, and 16*WC*FN launch columns.  Its
+// T0*T2 row fragments (16 positions each) are split over 4/WC wave rows,
+// its column fragments over WC wave columns, so each wave accumulates an
+// FM x FN grid of 16 x 16 MFMA tiles (FM = T0*T2*WC/4).  D > 1 packs D
+// neighbouring outputs along axis 2 into the columns: launch column
+// delta*coutr + c is output column c at axis-2 offset delta, computed with
+// the kernel widened to k2 + D - 1 taps whose weights are shifted copies
+// (zero outside the original taps).  Narrow outputs (the adjoint has only
+// 2*coils real columns) then reuse every staged operand D times more.
 struct TileCfg {
-  int T0, T2, WN;
+  int T0, T2, WC, FN, D;
 };
+
+// X-macro list of the instantiated shapes: X(id, T0, T2, WC, FN, D, pipelined
+// staging available, batched kernel available).
+#define HICU_TILES(X)            \
+  X(0, 1, 8, 1, 1, 1, 1, 1)      \
+  X(1, 1, 8, 1, 2, 1, 1, 1)      \
+  X(2, 1, 8, 1, 4, 1, 1, 1)      \
+  X(3, 1, 4, 1, 1, 1, 1, 0)      \
+  X(4, 1, 4, 1, 2, 1, 1, 0)      \
+  X(5, 1, 4, 1, 4, 1, 1, 0)      \
+  X(6, 1, 8, 2, 2, 1, 0, 0)      \
+  X(7, 1, 8, 2, 4, 1, 0, 0)      \
+  X(8, 1, 16, 2, 4, 1, 0, 0)     \
+  X(9, 1, 16, 1, 2, 1, 1, 0)     \
+  X(10, 1, 8, 1, 4, 2, 1, 0)     \
+  X(11, 1, 16, 1, 4, 2, 1, 0)    \
+  X(12, 1, 8, 1, 4, 4, 1, 0)     \
+  X(13, 2, 4, 1, 1, 1, 1, 1)     \
+  X(14, 2, 4, 1, 2, 1, 1, 1)     \
+  X(15, 2, 4, 1, 4, 1, 1, 1)     \
+  X(16, 2, 8, 1, 1, 1, 1, 0)     \
+  X(17, 2, 8, 1, 2, 1, 1, 0)     \
+  X(18, 2, 8, 1, 4, 1, 1, 0)     \
+  X(19, 2, 4, 2, 4, 1, 0, 0)     \
+  X(20, 2, 8, 2, 4, 1, 0, 0)     \
+  X(21, 2, 4, 1, 4, 4, 1, 0)     \
+  X(22, 2, 8, 1, 4, 4, 1, 0)     \
+  X(23, 2, 4, 1, 2, 2, 1, 0)     \
+  X(24, 2, 4, 1, 4, 2, 1, 0)     \
+  X(25, 2, 8, 1, 4, 2, 1, 0)
+
+constexpr int kNumTiles = 26;
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+TileCfg tile_cfg(int id);
+// Block columns of a shape.
+inline int block_cols(const TileCfg& t) { return 16 * t.WC * t.FN; }
 
 struct ConvPlan {
   int prec;
+  int tile;             // index into the shape list
   TileCfg t;
   ConvArgs a;
-  dim3 grid;
+  int64_t gx;           // position tiles
+  int gy;               // column blocks
   size_t lds_bytes;
 };
 
 // Weight layout of one contraction (shared by the weight builder and the
-// convolution kernel).
+// convolution kernel): [chunk][k0][k1][kb][ncolp][KB], the run over
+// (k2 + D - 1 taps, chunk channels, re/im) split into k-blocks of KB.
 struct WeightShape {
-  int chunk_c, nchunks, ps, nkb, ncolp, KB;
+  int chunk_c, nchunks, ps, nkb, ncolp, KB, D, cout;
   size_t elems;           // elements per part (hi or lo)
 };
 
-constexpr int kColPad = 64;  // weight columns padded to the widest tile
+constexpr int kColPad = 128;  // weight columns padded to the widest block
 
-WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total);
+WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total, int D = 1);
 
 // Arguments of the weight builder (one problem).
 struct PrepArgs {
   const float2* F;
   int p, nc, k0, k1, k2, mode, prec;
-  int chunk_c, ps, nkb, ncolp, KB, coutr_total;
+  int chunk_c, ps, nkb, ncolp, KB, coutr_total, D;
   int64_t total;
   void* B;
   void* Blo;
@@ -95,11 +142,16 @@ PrepArgs make_prep_args(int mode, int prec, const Geo& g, const float2* F, int p
 // One launch building the weights of `count` problems (args in device memory).
 int32_t launch_prep_weights_batch(const PrepArgs* args_dev, int count, int64_t max_total, hipStream_t st);
 
-TileCfg default_tile(int prec, const Geo& g, int coutr);
+// Default shape for a contraction with coutr real output columns (role 0
+// forward / line search, 1 adjoint).
+int default_tile(int prec, const Geo& g, int coutr, int role);
+// Axis-2 packing a shape id implies (its D).
+inline int tile_D(int id) { return tile_cfg(id).D; }
 
 // Fill the shape-dependent fields of plan->a (everything but pointers,
-// strides, org, validity box and epilogue options).
-int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, int nchunks,
+// strides, org, validity box and epilogue options).  ws must be built with
+// the shape's D.
+int32_t plan_conv(int prec, int tile, const int k[3], const WeightShape& ws, int nchunks,
                   const int64_t oe[3], int coutr, ConvPlan* plan);
 
 int32_t launch_conv(const ConvPlan& plan, hipStream_t st);
@@ -108,7 +160,7 @@ int32_t launch_conv(const ConvPlan& plan, hipStream_t st);
 // tile shape and precision (args and tile_start in device memory).
 struct BatchConvLaunch {
   int prec;
-  TileCfg t;
+  int tile;
   bool pipe;
   const ConvArgs* args;
   const int64_t* tile_start;
@@ -120,6 +172,10 @@ struct BatchConvLaunch {
 int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st);
 // Whether one channel chunk of this plan fits the register staging slots.
 bool conv_can_pipe(const ConvPlan& p);
+// Widest staging unit the arguments allow: V channels of a point are read
+// with 16-byte loads when the input is 16-byte aligned and the point
+// stride, chunk and channel base are multiples of V.
+int conv_vec(const ConvArgs& a);
 
 // Fixed-order sum of `count` doubles into *out (single block).
 int32_t launch_reduce(const double* part, int64_t count, double* out, hipStream_t st);

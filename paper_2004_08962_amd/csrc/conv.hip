@@ -24,19 +24,75 @@ template <> struct LdsElem<P_BF16X3> { using T = uint16_t; };
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-template <int PREC>
-__device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typename LdsElem<PREC>::T* lo,
-                                            int64_t off, float2 v) {
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats -> packed BF16 (round to nearest even; one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{x, y}, bf16x2_t));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Store 2V floats (V complex values, interleaved re/im) at LDS element
+// offset off: FP32 as is, BF16 rounded, split BF16 as hi and lo = v - hi.
+template <int PREC, int V>
+__device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typename LdsElem<PREC>::T* lo, int off,
+                                            const float (&v)[2 * V]) {
   if constexpr (PREC == P_F32) {
-    *reinterpret_cast<float2*>(hi + off) = v;
-  } else if constexpr (PREC == P_BF16) {
-    const uint32_t w = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-    *reinterpret_cast<uint32_t*>(hi + off) = w;
+    if constexpr (V == 4) {
+      *reinterpret_cast<float4_t*>(hi + off) = float4_t{v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<float4_t*>(hi + off + 4) = float4_t{v[4], v[5], v[6], v[7]};
+    } else if constexpr (V == 2) {
+      *reinterpret_cast<float4_t*>(hi + off) = float4_t{v[0], v[1], v[2], v[3]};
+    } else {
+      *reinterpret_cast<float2*>(hi + off) = make_float2(v[0], v[1]);
+    }
   } else {
-    const uint16_t hx = f2bf(v.x), hy = f2bf(v.y);
-    const uint16_t lx = f2bf(v.x - bf2f(hx)), ly = f2bf(v.y - bf2f(hy));
-    *reinterpret_cast<uint32_t*>(hi + off) = (uint32_t)hx | ((uint32_t)hy << 16);
-    *reinterpret_cast<uint32_t*>(lo + off) = (uint32_t)lx | ((uint32_t)ly << 16);
+    uint32_t w[V], wl[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      w[i] = pack_bf16(v[2 * i], v[2 * i + 1]);
+      if constexpr (PREC == P_BF16X3) wl[i] = pack_bf16(v[2 * i] - bf16_lo(w[i]), v[2 * i + 1] - bf16_hi(w[i]));
+    }
+    auto put = [&](uint16_t* dst, const uint32_t (&x)[V]) {
+      if constexpr (V == 4) *reinterpret_cast<u32x4_t*>(dst + off) = u32x4_t{x[0], x[1], x[2], x[3]};
+      else if constexpr (V == 2) *reinterpret_cast<u32x2_t*>(dst + off) = u32x2_t{x[0], x[1]};
+      else *reinterpret_cast<uint32_t*>(dst + off) = x[0];
+    };
+    put(hi, w);
+    if constexpr (PREC == P_BF16X3) put(lo, wl);
+  }
+}
+
+// V complex values from global memory at in + idx: nv = V loads them with
+// 16-byte loads, 0 < nv < V one by one (the rest zero), nv = 0 gives zeros.
+template <int V>
+__device__ __forceinline__ void load_unit(const float2* in, int64_t idx, int nv, float (&v)[2 * V]) {
+  if (nv == V) {
+    if constexpr (V == 1) {
+      const float2 t = in[idx];
+      v[0] = t.x;
+      v[1] = t.y;
+    } else {
+#pragma unroll
+      for (int h = 0; h < V / 2; ++h) {
+        const float4_t t = *reinterpret_cast<const float4_t*>(in + idx + 2 * h);
+        v[4 * h] = t[0];
+        v[4 * h + 1] = t[1];
+        v[4 * h + 2] = t[2];
+        v[4 * h + 3] = t[3];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      float2 t = make_float2(0.f, 0.f);
+      if (i < nv) t = in[idx + i];
+      v[2 * i] = t.x;
+      v[2 * i + 1] = t.y;
+    }
   }
 }
 
@@ -45,149 +101,207 @@ __device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typen
 // streamed and a chunk fits in kStageSlots complex values per thread).
 constexpr int kStageSlots = 16;
 
-// One output tile: positions tile bx (of gx along the position grid) and
-// column block by.  Shared by the per-problem kernel and the persistent
-// batched kernel.
-template <int PREC, int T0, int T2, int WN, bool PIPE>
+// Operand fragments of one k-block for one wave: FM row fragments from LDS,
+// FN column fragments of the weights (L1/L2), hi and (split precision) lo.
+template <int PREC, int FM, int FN> struct Frags;
+template <int FM, int FN> struct Frags<P_F32, FM, FN> {
+  float4_t a[FM], b[FN];
+};
+template <int FM, int FN> struct Frags<P_BF16, FM, FN> {
+  bf16x8_t a[FM], b[FN];
+};
+template <int FM, int FN> struct Frags<P_BF16X3, FM, FN> {
+  bf16x8_t a[FM], b[FN], al[FM], bl[FN];
+};
+
+// Stage channels [cbase, cbase + chunk_c) of the halo of one tile into LDS,
+// V channels of one point per unit.  Units form a grid of rows (hh0, hh1)
+// by columns (hh2, channel group); when a row of units fits the 256 threads
+// each thread keeps its column (and that column's index arithmetic) and
+// steps over rows, else units are enumerated one by one.
+template <int PREC, int V>
+__device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<PREC>::T* lds,
+                                            typename LdsElem<PREC>::T* lds_lo, const int cbase, const int64_t base0,
+                                            const int64_t base1, const int64_t base2, const int tid) {
+  const int cpr = a.chunk_c / V;
+  const int ncol = a.h[2] * cpr;
+  const int rows = a.h[0] * a.h[1];
+  const int coff = cbase - a.chan_base;
+  auto unit = [&](const int hh0, const int hh1, const int hh2, const int cq) {
+    const int64_t i0 = a.org[0] + base0 + hh0, i1 = a.org[1] + base1 + hh1, i2 = a.org[2] + base2 + hh2;
+    const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
+                    i2 < a.vhi[2];
+    const int nv = ok ? max(0, min(V, a.cin - (cbase + cq * V))) : 0;
+    float v[2 * V];
+    load_unit<V>(a.in, nv ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + coff + cq * V : 0, nv, v);
+    stage_store<PREC, V>(lds, lds_lo, (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V, v);
+  };
+  if (ncol <= 256) {
+    const int R = 256 / ncol;
+    const int r0 = tid / ncol, col = tid - r0 * ncol;
+    if (r0 >= R) return;
+    const int hh2 = col / cpr, cq = col - hh2 * cpr;
+    int hh0 = r0 / a.h[1], hh1 = r0 - hh0 * a.h[1];
+    for (int row = r0; row < rows; row += R) {
+      unit(hh0, hh1, hh2, cq);
+      hh1 += R;
+      while (hh1 >= a.h[1]) {
+        hh1 -= a.h[1];
+        ++hh0;
+      }
+    }
+  } else {
+    for (int e = tid; e < rows * ncol; e += 256) {
+      const int row = e / ncol, col = e - row * ncol;
+      const int hh0 = row / a.h[1], hh1 = row - hh0 * a.h[1];
+      const int hh2 = col / cpr, cq = col - hh2 * cpr;
+      unit(hh0, hh1, hh2, cq);
+    }
+  }
+}
+
+// One output tile: position tile bx (of gx) and column block by.  Shared by
+// the per-problem kernel and the persistent batched kernel.
+template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
 __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, const int by, const int64_t gx,
                                           unsigned char* smem) {
   constexpr int KB = kblock_of(PREC);
   constexpr int NFRAG = T0 * T2;
-  static_assert(NFRAG % 4 == 0, "tile must give each wave whole fragments");
-  constexpr int WM = NFRAG / 4;
+  constexpr int WR = 4 / WC;
+  static_assert(4 % WC == 0 && NFRAG % WR == 0, "tile must give each wave whole fragments");
+  constexpr int FM = NFRAG / WR;
+  constexpr int BC = 16 * WC * FN;
   constexpr bool SPLIT = PREC == P_BF16X3;
   using E = typename LdsElem<PREC>::T;
 
   E* lds = reinterpret_cast<E*>(smem);
-  const int64_t lds_elems = (int64_t)a.h[0] * a.h[1] * a.rs;
+  const int lds_elems = a.h[0] * a.h[1] * a.rs;
   E* lds_lo = lds + lds_elems;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
+  const int wr = wave / WC, wc = wave % WC;
   const int64_t t2i = bx % a.nt[2];
   const int64_t t1i = (bx / a.nt[2]) % a.nt[1];
   const int64_t t0i = bx / (a.nt[2] * a.nt[1]);
-  const int64_t base0 = t0i * T0, base1 = t1i * 16, base2 = t2i * T2;
-  const int n0 = a.col0 + by * (16 * WN);
+  const int64_t base0 = t0i * T0, base1 = t1i * 16, base2 = t2i * (T2 * D);
+  const int n0w = a.col0 + by * BC + wc * 16 * FN;  // first weight column of this wave
 
-  // Row tails (read with zero weights) must hold finite values.
+  // Row tails and the padding of each point past its 2 chunk_c entries are
+  // read with zero weights and must hold finite values.
   {
     const int tail = a.rs - a.h[2] * a.ps;
     const int nrows = a.h[0] * a.h[1];
     for (int e = tid; e < nrows * tail; e += 256) {
-      const int64_t off = (int64_t)(e / tail) * a.rs + a.h[2] * a.ps + (e % tail);
+      const int off = (e / tail) * a.rs + a.h[2] * a.ps + (e % tail);
       lds[off] = E(0);
       if constexpr (SPLIT) lds_lo[off] = E(0);
     }
+    const int pad = a.ps - 2 * a.chunk_c;
+    if (pad > 0) {
+      const int npts = nrows * a.h[2];
+      for (int e = tid; e < npts * pad; e += 256) {
+        const int pt = e / pad, r = pt / a.h[2];
+        const int off = r * a.rs + (pt - r * a.h[2]) * a.ps + 2 * a.chunk_c + (e - pt * pad);
+        lds[off] = E(0);
+        if constexpr (SPLIT) lds_lo[off] = E(0);
+      }
+    }
   }
 
-  float4_t acc[WM][WN];
+  float4_t acc[FM][FN];
 #pragma unroll
-  for (int f = 0; f < WM; ++f)
+  for (int f = 0; f < FM; ++f)
 #pragma unroll
-    for (int j = 0; j < WN; ++j) acc[f][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FN; ++j) acc[f][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
   // Per-fragment LDS offsets of this lane's operand (without kernel shift).
-  int frag_off[WM];
+  int frag_off[FM];
 #pragma unroll
-  for (int f = 0; f < WM; ++f) {
-    const int fg = wave * WM + f;
+  for (int f = 0; f < FM; ++f) {
+    const int fg = wr * FM + f;
     const int fa = fg / T2, fc = fg % T2;
-    frag_off[f] = (fa * a.h[1] + m) * a.rs + fc * a.ps + g * (KB / 4);
+    frag_off[f] = (fa * a.h[1] + m) * a.rs + fc * D * a.ps + g * (KB / 4);
   }
 
   const int half_ps = a.ps >> 1;
-  const int64_t npts_halo = (int64_t)a.h[0] * a.h[1] * a.h[2];
-  const int64_t nstage = npts_halo * half_ps;
+  const int npts_halo = a.h[0] * a.h[1] * a.h[2];
+  const int nstage = npts_halo * half_ps;
+  const int nkb = a.nkb, nk1 = a.k[1];
+  const int total = a.k[0] * nk1 * nkb;
 
-  auto compute_chunk = [&](const int chg) {
-    for (int k0 = 0; k0 < a.k[0]; ++k0) {
-      for (int k1 = 0; k1 < a.k[1]; ++k1) {
-        const int shift = (k0 * a.h[1] + k1) * a.rs;
-        const size_t wrow = ((((size_t)chg * a.k[0] + k0) * a.k[1] + k1) * a.nkb) * a.ncolp;
-        for (int t = 0; t < a.nkb; ++t) {
-          const size_t wt = (wrow + (size_t)t * a.ncolp + n0 + m) * KB + g * (KB / 4);
-          if constexpr (PREC == P_F32) {
-            float4_t av[WM], bv[WN];
+  // Operands of flattened k-step i = ((k0 * k1n) + k1) * nkb + t of chunk chg.
+  auto load_frags = [&](Frags<PREC, FM, FN>& fr, const int chg, const int i) {
+    const int kk = i / nkb, t = i - kk * nkb;
+    const int k0 = kk / nk1, k1 = kk - k0 * nk1;
+    const int shift = (k0 * a.h[1] + k1) * a.rs + t * KB;
+    const size_t wt = ((((size_t)chg * a.k[0] + k0) * nk1 + k1) * nkb + t) * a.ncolp * KB +
+                      (size_t)(n0w + m) * KB + g * (KB / 4);
+    if constexpr (PREC == P_F32) {
+      const float* Bp = reinterpret_cast<const float*>(a.B);
 #pragma unroll
-            for (int f = 0; f < WM; ++f)
-              av[f] = *reinterpret_cast<const float4_t*>(lds + frag_off[f] + shift + t * KB);
-            const float* Bp = reinterpret_cast<const float*>(a.B);
+      for (int f = 0; f < FM; ++f) fr.a[f] = *reinterpret_cast<const float4_t*>(lds + frag_off[f] + shift);
 #pragma unroll
-            for (int j = 0; j < WN; ++j)
-              bv[j] = *reinterpret_cast<const float4_t*>(Bp + wt + (size_t)j * 16 * KB);
+      for (int j = 0; j < FN; ++j) fr.b[j] = *reinterpret_cast<const float4_t*>(Bp + wt + (size_t)j * 16 * KB);
+    } else {
+      const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
 #pragma unroll
-            for (int f = 0; f < WM; ++f)
+      for (int f = 0; f < FM; ++f)
+        fr.a[f] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(lds + frag_off[f] + shift));
 #pragma unroll
-              for (int j = 0; j < WN; ++j) {
-                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][0], bv[j][0], acc[f][j], 0, 0, 0);
-                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][1], bv[j][1], acc[f][j], 0, 0, 0);
-                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][2], bv[j][2], acc[f][j], 0, 0, 0);
-                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][3], bv[j][3], acc[f][j], 0, 0, 0);
-              }
-          } else {
-            bf16x8_t av[WM], bv[WN];
+      for (int j = 0; j < FN; ++j)
+        fr.b[j] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(Bp + wt + (size_t)j * 16 * KB));
+      if constexpr (SPLIT) {
+        const uint16_t* Bl = reinterpret_cast<const uint16_t*>(a.Blo);
 #pragma unroll
-            for (int f = 0; f < WM; ++f)
-              av[f] = __builtin_bit_cast(
-                  bf16x8_t, *reinterpret_cast<const u32x4_t*>(lds + frag_off[f] + shift + t * KB));
-            const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
+        for (int f = 0; f < FM; ++f)
+          fr.al[f] =
+              __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(lds_lo + frag_off[f] + shift));
 #pragma unroll
-            for (int j = 0; j < WN; ++j)
-              bv[j] = __builtin_bit_cast(bf16x8_t,
-                                         *reinterpret_cast<const u32x4_t*>(Bp + wt + (size_t)j * 16 * KB));
+        for (int j = 0; j < FN; ++j)
+          fr.bl[j] =
+              __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(Bl + wt + (size_t)j * 16 * KB));
+      }
+    }
+  };
+  auto mma = [&](const Frags<PREC, FM, FN>& fr) {
 #pragma unroll
-            for (int f = 0; f < WM; ++f)
+    for (int f = 0; f < FM; ++f)
 #pragma unroll
-              for (int j = 0; j < WN; ++j)
-                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[f], bv[j], acc[f][j], 0, 0, 0);
-            if constexpr (SPLIT) {
-              bf16x8_t al[WM], bl[WN];
-#pragma unroll
-              for (int f = 0; f < WM; ++f)
-                al[f] = __builtin_bit_cast(
-                    bf16x8_t, *reinterpret_cast<const u32x4_t*>(lds_lo + frag_off[f] + shift + t * KB));
-              const uint16_t* Bl = reinterpret_cast<const uint16_t*>(a.Blo);
-#pragma unroll
-              for (int j = 0; j < WN; ++j)
-                bl[j] = __builtin_bit_cast(
-                    bf16x8_t, *reinterpret_cast<const u32x4_t*>(Bl + wt + (size_t)j * 16 * KB));
-#pragma unroll
-              for (int f = 0; f < WM; ++f)
-#pragma unroll
-                for (int j = 0; j < WN; ++j) {
-                  acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[f], bl[j], acc[f][j], 0, 0, 0);
-                  acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], bv[j], acc[f][j], 0, 0, 0);
-                }
-            }
+      for (int j = 0; j < FN; ++j) {
+        if constexpr (PREC == P_F32) {
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[f][0], fr.b[j][0], acc[f][j], 0, 0, 0);
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[f][1], fr.b[j][1], acc[f][j], 0, 0, 0);
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[f][2], fr.b[j][2], acc[f][j], 0, 0, 0);
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[f][3], fr.b[j][3], acc[f][j], 0, 0, 0);
+        } else {
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.a[f], fr.b[j], acc[f][j], 0, 0, 0);
+          if constexpr (SPLIT) {
+            acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.a[f], fr.bl[j], acc[f][j], 0, 0, 0);
+            acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.al[f], fr.b[j], acc[f][j], 0, 0, 0);
           }
         }
       }
+  };
+  // The operands of step i + 1 are fetched while step i multiplies.
+  auto compute_chunk = [&](const int chg) {
+    Frags<PREC, FM, FN> p0, p1;
+    load_frags(p0, chg, 0);
+    for (int i = 0; i < total; i += 2) {
+      if (i + 1 < total) load_frags(p1, chg, i + 1);
+      mma(p0);
+      if (i + 1 >= total) break;
+      if (i + 2 < total) load_frags(p0, chg, i + 2);
+      mma(p1);
     }
   };
 
   if constexpr (!PIPE) {
     for (int ch = 0; ch < a.nchunks; ++ch) {
       const int chg = a.ch0 + ch;
-      const int cbase = chg * a.chunk_c;
       __syncthreads();
-      for (int64_t e = tid; e < nstage; e += 256) {
-        const int cs = (int)(e % half_ps);
-        const int64_t pt = e / half_ps;
-        const int hh2 = (int)(pt % a.h[2]);
-        const int64_t q = pt / a.h[2];
-        const int hh1 = (int)(q % a.h[1]);
-        const int hh0 = (int)(q / a.h[1]);
-        const int64_t i0 = a.org[0] + base0 + hh0;
-        const int64_t i1 = a.org[1] + base1 + hh1;
-        const int64_t i2 = a.org[2] + base2 + hh2;
-        const int ci = cbase + cs;
-        float2 v = make_float2(0.f, 0.f);
-        if (cs < a.chunk_c && ci < a.cin && i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] &&
-            i1 < a.vhi[1] && i2 >= a.vlo[2] && i2 < a.vhi[2])
-          v = a.in[i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + (ci - a.chan_base)];
-        const int64_t off = ((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs;
-        stage_store<PREC>(lds, lds_lo, off, v);
-      }
+      if (a.vec == 4) stage_units<PREC, 4>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
+      else if (a.vec == 2) stage_units<PREC, 2>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
+      else stage_units<PREC, 1>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
       __syncthreads();
       compute_chunk(chg);
     }
@@ -199,24 +313,24 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     int loff[kStageSlots], csl[kStageSlots];
 #pragma unroll
     for (int i = 0; i < kStageSlots; ++i) {
-      const int64_t e = tid + 256 * i;
+      const int e = tid + 256 * i;
       goff[i] = -2;
       loff[i] = 0;
       csl[i] = 0;
       if (e < nstage) {
-        const int cs = (int)(e % half_ps);
-        const int64_t pt = e / half_ps;
-        const int hh2 = (int)(pt % a.h[2]);
-        const int64_t q = pt / a.h[2];
-        const int hh1 = (int)(q % a.h[1]);
-        const int hh0 = (int)(q / a.h[1]);
+        const int cs = e % half_ps;
+        const int pt = e / half_ps;
+        const int hh2 = pt % a.h[2];
+        const int q = pt / a.h[2];
+        const int hh1 = q % a.h[1];
+        const int hh0 = q / a.h[1];
         const int64_t i0 = a.org[0] + base0 + hh0;
         const int64_t i1 = a.org[1] + base1 + hh1;
         const int64_t i2 = a.org[2] + base2 + hh2;
         const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
                         i2 < a.vhi[2];
         goff[i] = ok ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] : -1;
-        loff[i] = (int)(((int64_t)hh0 * a.h[1] + hh1) * a.rs + (int64_t)hh2 * a.ps + 2 * cs);
+        loff[i] = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cs;
         csl[i] = cs;
       }
     }
@@ -234,7 +348,10 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     auto store = [&]() {
 #pragma unroll
       for (int i = 0; i < kStageSlots; ++i)
-        if (goff[i] != -2) stage_store<PREC>(lds, lds_lo, loff[i], buf[i]);
+        if (goff[i] != -2) {
+          const float v[2] = {buf[i].x, buf[i].y};
+          stage_store<PREC, 1>(lds, lds_lo, loff[i], v);
+        }
     };
     load(a.ch0);
     __syncthreads();  // row tails zeroed before the first chunk lands
@@ -252,28 +369,32 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     }
   }
 
-  // Epilogue: lane holds rows 4g..4g+3 (positions along axis 1) of column m.
+  // Epilogue: lane holds rows 4g..4g+3 (positions along axis 1) of column m
+  // of each of its FM x FN tiles.  Launch column lc = delta * coutr + c.
   double ssq = 0.0;
 #pragma unroll
-  for (int f = 0; f < WM; ++f) {
-    const int fg = wave * WM + f;
-    const int64_t p0 = base0 + fg / T2, p2 = base2 + fg % T2;
+  for (int f = 0; f < FM; ++f) {
+    const int fg = wr * FM + f;
+    const int64_t p0 = base0 + fg / T2, p2b = base2 + (int64_t)(fg % T2) * D;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t p1 = base1 + 4 * g + i;
-      const bool pv = p0 < a.oe[0] && p1 < a.oe[1] && p2 < a.oe[2];
-      if (!pv) continue;
-      bool masked = false;
-      if (a.mask)
-        masked = a.mask[(a.morg[0] + p0) * a.ms[0] + (a.morg[1] + p1) * a.ms[1] + (a.morg[2] + p2) * a.ms[2]] != 0;
-      const int64_t ob = 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]);
+    for (int j = 0; j < FN; ++j) {
+      const int lc = by * BC + (wc * FN + j) * 16 + m;
+      if (lc >= D * a.coutr) continue;
+      const int delta = D == 1 ? 0 : lc / a.coutr;
+      const int c = lc - delta * a.coutr;
+      const int64_t p2 = p2b + delta;
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int lc = by * (16 * WN) + j * 16 + m;
-        if (lc >= a.coutr) continue;
+      for (int i = 0; i < 4; ++i) {
+        const int64_t p1 = base1 + 4 * g + i;
+        const bool pv = p0 < a.oe[0] && p1 < a.oe[1] && p2 < a.oe[2];
+        if (!pv) continue;
+        bool masked = false;
+        if (a.mask)
+          masked =
+              a.mask[(a.morg[0] + p0) * a.ms[0] + (a.morg[1] + p1) * a.ms[1] + (a.morg[2] + p2) * a.ms[2]] != 0;
         float v = masked ? 0.f : acc[f][j][i] * a.scale;
         if (a.out) {
-          float* dst = a.out + ob + lc;
+          float* dst = a.out + 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]) + c;
           if (a.accumulate) v += *dst;
           *dst = v;
         }
@@ -288,10 +409,21 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   }
 }
 
-template <int PREC, int T0, int T2, int WN, bool PIPE>
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
+// Workgroups are dispatched to the 8 XCDs round-robin; remap the linear id so
+// that each XCD (own L2) processes a contiguous run of work items: the
+// column blocks of one position tile and neighbouring tiles along axis 2
+// then share staged input through the same L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t W) {
+  const int64_t per = W / 8, rem = W % 8;
+  const int64_t xcd = w % 8, idx = w / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, int64_t gx, int gy) {
   extern __shared__ __align__(16) unsigned char smem[];
-  conv_tile<PREC, T0, T2, WN, PIPE>(a, blockIdx.x, blockIdx.y, gridDim.x, smem);
+  const int64_t lin = xcd_remap(blockIdx.x, gx * gy);
+  conv_tile<PREC, T0, T2, WC, FN, D, PIPE>(a, lin / gy, (int)(lin % gy), gx, smem);
 }
 
 // Persistent batched launch: the work list is every (position tile, column
@@ -299,7 +431,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
 // q.  Workgroups stride over the list, so problems of any size and channel
 // count share one launch.  Each item runs the same tile code as the
 // per-problem kernel, so results are bitwise identical.
-template <int PREC, int T0, int T2, int WN, bool PIPE>
+template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
 __global__ __launch_bounds__(256) void conv_batch_kernel(const ConvArgs* args, const int64_t* tile_start, int nprob,
                                                          int64_t total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -313,7 +445,7 @@ __global__ __launch_bounds__(256) void conv_batch_kernel(const ConvArgs* args, c
     const ConvArgs& a = args[lo];
     const int64_t local = it - tile_start[lo];
     const int64_t gx = a.nt[0] * a.nt[1] * a.nt[2];
-    conv_tile<PREC, T0, T2, WN, PIPE>(a, local % gx, (int)(local / gx), gx, smem);
+    conv_tile<PREC, T0, T2, WC, FN, D, PIPE>(a, local % gx, (int)(local / gx), gx, smem);
     __syncthreads();  // the next item reuses LDS
   }
 }
@@ -333,11 +465,13 @@ __device__ __forceinline__ void prep_element(const PrepArgs& a, const int64_t e)
   const int k0 = (int)(r % a.k0);
   const int ch = (int)(r / a.k0);
   const int run = t * a.KB + kbe;
-  const int kk2 = run / a.ps, el = run % a.ps;
+  // launch column col = delta * coutr_total + c uses the taps shifted by delta
+  const int delta = col / a.coutr_total, c = col - delta * a.coutr_total;
+  const int kk2 = run / a.ps - delta, el = run % a.ps;
   float v = 0.f;
-  if (kk2 < a.k2 && el < 2 * a.chunk_c && col < a.coutr_total) {
+  if (delta < a.D && kk2 >= 0 && kk2 < a.k2 && el < 2 * a.chunk_c) {
     const int ci = ch * a.chunk_c + (el >> 1), ri = el & 1;
-    const int co = col >> 1, ro = col & 1;
+    const int co = c >> 1, ro = c & 1;
     if (a.mode == 0) {
       if (ci < a.nc && co < a.p) {
         const int64_t row = (((int64_t)k0 * a.k1 + k1) * a.k2 + kk2) * a.nc + ci;
@@ -388,14 +522,34 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double* part, int64_
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total) {
+TileCfg tile_cfg(int id) {
+  static const TileCfg table[kNumTiles] = {
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) {T0, T2, WC, FN, D},
+      HICU_TILES(HICU_TILE_ROW)
+#undef HICU_TILE_ROW
+  };
+  return (id >= 0 && id < kNumTiles) ? table[id] : TileCfg{0, 0, 0, 0, 0};
+}
+
+static bool tile_pipe_ok(int id) {
+  static const bool table[kNumTiles] = {
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) P != 0,
+      HICU_TILES(HICU_TILE_ROW)
+#undef HICU_TILE_ROW
+  };
+  return id >= 0 && id < kNumTiles && table[id];
+}
+
+WeightShape weight_shape(int prec, const int k[3], int cin, int chunk_c, int coutr_total, int D) {
   WeightShape w;
   w.KB = kblock_of(prec);
+  w.D = D;
+  w.cout = coutr_total;
   w.chunk_c = chunk_c;
   w.nchunks = (int)cdiv(cin, chunk_c);
   w.ps = (int)rup(2 * chunk_c, 8);
-  w.nkb = (int)cdiv((int64_t)k[2] * w.ps, w.KB);
-  w.ncolp = (int)rup(coutr_total, kColPad);
+  w.nkb = (int)cdiv((int64_t)(k[2] + D - 1) * w.ps, w.KB);
+  w.ncolp = (int)rup((int64_t)D * coutr_total, kColPad);
   w.elems = (size_t)w.nchunks * k[0] * k[1] * w.nkb * w.ncolp * w.KB;
   return w;
 }
@@ -417,6 +571,7 @@ PrepArgs make_prep_args(int mode, int prec, const Geo& g, const float2* F, int p
   a.ncolp = ws.ncolp;
   a.KB = ws.KB;
   a.coutr_total = mode == 0 ? 2 * p : 2 * g.nc;
+  a.D = ws.D;
   a.total = (int64_t)ws.elems;
   a.B = B;
   a.Blo = Blo;
@@ -426,6 +581,7 @@ PrepArgs make_prep_args(int mode, int prec, const Geo& g, const float2* F, int p
 int32_t launch_prep_weights(int mode, int prec, const Geo& g, const float2* F, int p,
                             const WeightShape& ws, void* B, void* Blo, hipStream_t st) {
   const PrepArgs a = make_prep_args(mode, prec, g, F, p, ws, B, Blo);
+  if (ws.cout != a.coutr_total) return HICU_ERR_SHAPE;
   const int64_t blocks = std::min<int64_t>(cdiv(a.total, 256), 8192);
   hipLaunchKernelGGL(prep_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   HICU_HIP_TRY(hipGetLastError());
@@ -440,40 +596,72 @@ int32_t launch_prep_weights_batch(const PrepArgs* args_dev, int count, int64_t m
   return HICU_OK;
 }
 
-template <int PREC, int T0, int T2, int WN, bool PIPE>
-static void launch_batch_inst(const BatchConvLaunch& b, hipStream_t st) {
-  hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WN, PIPE>), dim3(b.grid), dim3(256), b.lds_bytes, st, b.args,
-                     b.tile_start, b.nprob, b.total);
+static int64_t stage_elems(const ConvPlan& p) {
+  return (int64_t)p.a.h[0] * p.a.h[1] * p.a.h[2] * (p.a.ps / 2);
 }
 
-template <int PREC, int T0, int T2, bool PIPE>
-static void launch_batch_wn(const BatchConvLaunch& b, hipStream_t st) {
-  switch (b.t.WN) {
-    case 1: launch_batch_inst<PREC, T0, T2, 1, PIPE>(b, st); break;
-    case 2: launch_batch_inst<PREC, T0, T2, 2, PIPE>(b, st); break;
-    default: launch_batch_inst<PREC, T0, T2, 4, PIPE>(b, st); break;
+bool conv_can_pipe(const ConvPlan& p) { return tile_pipe_ok(p.tile) && stage_elems(p) <= 256 * kStageSlots; }
+
+int conv_vec(const ConvArgs& a) {
+  const bool aligned = (reinterpret_cast<uintptr_t>(a.in) & 15) == 0;
+  for (int V : {4, 2}) {
+    if (aligned && a.is[2] % V == 0 && a.chunk_c % V == 0 && a.chan_base % V == 0) return V;
   }
+  return 1;
 }
 
-template <int PREC, int T0, int T2>
-static void launch_batch_pipe(const BatchConvLaunch& b, hipStream_t st) {
-  if (b.pipe) launch_batch_wn<PREC, T0, T2, true>(b, st);
-  else launch_batch_wn<PREC, T0, T2, false>(b, st);
+// Per-problem launches: one 1-D grid of gx * gy workgroups.
+template <int PREC>
+static int32_t launch_prec(const ConvPlan& p, bool pipe, hipStream_t st) {
+  const dim3 grid((unsigned)(p.gx * p.gy)), block(256);
+  switch (p.tile) {
+#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, P, B)                                                              \
+  case id:                                                                                                     \
+    if constexpr (P != 0) {                                                                                    \
+      if (pipe) {                                                                                              \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, true>), grid, block, p.lds_bytes, st, p.a,     \
+                           p.gx, p.gy);                                                                        \
+        break;                                                                                                 \
+      }                                                                                                        \
+    }                                                                                                          \
+    hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false>), grid, block, p.lds_bytes, st, p.a, p.gx,  \
+                       p.gy);                                                                                  \
+    break;
+    HICU_TILES(HICU_TILE_CASE)
+#undef HICU_TILE_CASE
+    default:
+      return HICU_ERR_UNSUPPORTED;
+  }
+  return HICU_OK;
 }
 
 template <int PREC>
 static int32_t launch_batch_prec(const BatchConvLaunch& b, hipStream_t st) {
-  const int T0 = b.t.T0, T2 = b.t.T2;
-  if (T0 == 1 && T2 == 4) launch_batch_pipe<PREC, 1, 4>(b, st);
-  else if (T0 == 1 && T2 == 8) launch_batch_pipe<PREC, 1, 8>(b, st);
-  else if (T0 == 2 && T2 == 4) launch_batch_pipe<PREC, 2, 4>(b, st);
-  else if (T0 == 2 && T2 == 8) launch_batch_pipe<PREC, 2, 8>(b, st);
-  else return HICU_ERR_UNSUPPORTED;
+  const dim3 grid(b.grid), block(256);
+  switch (b.tile) {
+#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, P, B)                                                            \
+  case id:                                                                                                   \
+    if constexpr (B != 0) {                                                                                  \
+      if (b.pipe)                                                                                            \
+        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, true>), grid, block, b.lds_bytes, st,  \
+                           b.args, b.tile_start, b.nprob, b.total);                                          \
+      else                                                                                                   \
+        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, false>), grid, block, b.lds_bytes, st, \
+                           b.args, b.tile_start, b.nprob, b.total);                                          \
+      break;                                                                                                 \
+    }                                                                                                        \
+    return HICU_ERR_UNSUPPORTED;
+    HICU_TILES(HICU_TILE_CASE)
+#undef HICU_TILE_CASE
+    default:
+      return HICU_ERR_UNSUPPORTED;
+  }
   return HICU_OK;
 }
 
 int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
   if (b.nprob < 1 || b.total < 1 || b.grid < 1) return HICU_ERR_ARG;
+  if (b.lds_bytes > kMaxLds) return HICU_ERR_UNSUPPORTED;
   int32_t s;
   if (b.prec == P_F32) s = launch_batch_prec<P_F32>(b, st);
   else if (b.prec == P_BF16) s = launch_batch_prec<P_BF16>(b, st);
@@ -483,16 +671,21 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
   return HICU_OK;
 }
 
-bool conv_can_pipe(const ConvPlan& p) {
-  const int64_t nstage = (int64_t)p.a.h[0] * p.a.h[1] * p.a.h[2] * (p.a.ps / 2);
-  return nstage <= 256 * kStageSlots;
-}
-
-TileCfg default_tile(int prec, const Geo& g, int coutr) {
+// Shapes tried first: the widest column block the output fills, D > 1 for
+// narrow outputs when the kernel has at least 3 taps along axis 2 (the
+// packing lengthens the reduction by (k2 + D - 1) / k2).
+int default_tile(int prec, const Geo& g, int coutr, int role) {
   (void)prec;
-  const int WN = coutr <= 16 ? 1 : (coutr <= 32 ? 2 : 4);
-  if (g.k[0] == 1) return TileCfg{1, 8, WN};
-  return TileCfg{2, 4, WN};
+  const bool is3d = g.k[0] > 1;
+  const int frags = (int)cdiv(coutr, 16);
+  if (role == 1 && g.k[2] >= 3 && frags <= 2) {
+    if (frags == 1) return is3d ? 21 : 12;
+    return is3d ? 24 : 10;
+  }
+  if (frags >= 8) return is3d ? 19 : 7;
+  if (frags >= 3) return is3d ? 15 : 2;
+  if (frags == 2) return is3d ? 14 : 1;
+  return is3d ? 13 : 0;
 }
 
 static int pick_rs(int prec, int need) {
@@ -506,11 +699,14 @@ static int pick_rs(int prec, int need) {
   return rs;
 }
 
-int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, int nchunks,
+int32_t plan_conv(int prec, int tile, const int k[3], const WeightShape& ws, int nchunks,
                   const int64_t oe[3], int coutr, ConvPlan* plan) {
-  if (t.T0 < 1 || t.T2 < 1 || (t.T0 * t.T2) % 4 != 0 || t.WN < 1 || t.WN > 4) return HICU_ERR_ARG;
+  const TileCfg t = tile_cfg(tile);
+  if (t.T0 < 1) return HICU_ERR_ARG;
+  if (ws.D != t.D) return HICU_ERR_ARG;
   ConvArgs& a = plan->a;
   plan->prec = prec;
+  plan->tile = tile;
   plan->t = t;
   a.chunk_c = ws.chunk_c;
   a.chan_base = 0;
@@ -521,65 +717,48 @@ int32_t plan_conv(int prec, TileCfg t, const int k[3], const WeightShape& ws, in
   for (int i = 0; i < 3; ++i) a.k[i] = k[i];
   a.h[0] = t.T0 + k[0] - 1;
   a.h[1] = 16 + k[1] - 1;
-  a.h[2] = t.T2 + k[2] - 1;
-  const int need = (t.T2 - 1) * ws.ps + ws.nkb * ws.KB;
+  a.h[2] = t.T2 * t.D + k[2] - 1;
+  const int need = (t.T2 - 1) * t.D * ws.ps + ws.nkb * ws.KB;
   a.rs = pick_rs(prec, need);
   const size_t esize = prec == P_F32 ? 4 : 2;
   plan->lds_bytes = (size_t)a.h[0] * a.h[1] * a.rs * esize * (prec == P_BF16X3 ? 2 : 1);
-  if (plan->lds_bytes > 65536) return HICU_ERR_UNSUPPORTED;
+  if (plan->lds_bytes > kMaxLds) return HICU_ERR_UNSUPPORTED;
   a.oe[0] = oe[0];
   a.oe[1] = oe[1];
   a.oe[2] = oe[2];
   a.nt[0] = cdiv(oe[0], t.T0);
   a.nt[1] = cdiv(oe[1], 16);
-  a.nt[2] = cdiv(oe[2], t.T2);
+  a.nt[2] = cdiv(oe[2], (int64_t)t.T2 * t.D);
   const int64_t gx = a.nt[0] * a.nt[1] * a.nt[2];
-  const int64_t gy = cdiv(coutr, 16 * t.WN);
-  if (gx <= 0 || gx > 0x7fffffff || gy <= 0 || gy > 65535) return HICU_ERR_SHAPE;
+  const int64_t gy = cdiv((int64_t)t.D * coutr, block_cols(t));
+  if (gx <= 0 || gy <= 0 || gy > 65535 || gx * gy > 0x7fffffff) return HICU_ERR_SHAPE;
   a.coutr = coutr;
-  plan->grid = dim3((unsigned)gx, (unsigned)gy, 1);
-  return HICU_OK;
-}
-
-template <int PREC, int T0, int T2, bool PIPE>
-static void launch_wn(const ConvPlan& p, hipStream_t st) {
-  switch (p.t.WN) {
-    case 1: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 1, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
-    case 2: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 2, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
-    default: hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, 4, PIPE>), p.grid, dim3(256), p.lds_bytes, st, p.a); break;
-  }
-}
-
-template <int PREC, int T0, int T2>
-static void launch_pipe(const ConvPlan& p, hipStream_t st) {
-  const int64_t nstage = (int64_t)p.a.h[0] * p.a.h[1] * p.a.h[2] * (p.a.ps / 2);
-  if (p.a.nchunks > 1 && nstage <= 256 * kStageSlots) launch_wn<PREC, T0, T2, true>(p, st);
-  else launch_wn<PREC, T0, T2, false>(p, st);
-}
-
-template <int PREC>
-static int32_t launch_prec(const ConvPlan& p, hipStream_t st) {
-  const int T0 = p.t.T0, T2 = p.t.T2;
-  if (T0 == 1 && T2 == 4) launch_pipe<PREC, 1, 4>(p, st);
-  else if (T0 == 1 && T2 == 8) launch_pipe<PREC, 1, 8>(p, st);
-  else if (T0 == 2 && T2 == 4) launch_pipe<PREC, 2, 4>(p, st);
-  else if (T0 == 2 && T2 == 8) launch_pipe<PREC, 2, 8>(p, st);
-  else return HICU_ERR_UNSUPPORTED;
+  plan->gx = gx;
+  plan->gy = (int)gy;
   return HICU_OK;
 }
 
 int32_t launch_conv(const ConvPlan& p, hipStream_t st) {
   // Host-side guard of every index the kernel forms from its arguments.
   const ConvArgs& a = p.a;
-  if ((int64_t)a.col0 + (int64_t)p.grid.y * 16 * p.t.WN > a.ncolp) return HICU_ERR_SHAPE;
+  const TileCfg t = tile_cfg(p.tile);
+  if (t.T0 < 1 || t.D != p.t.D) return HICU_ERR_ARG;
+  if ((int64_t)a.col0 + (int64_t)p.gy * block_cols(t) > a.ncolp) return HICU_ERR_SHAPE;
+  if ((int64_t)p.gy * block_cols(t) < (int64_t)t.D * a.coutr) return HICU_ERR_SHAPE;
   if (a.ps < 2 * a.chunk_c || a.ps % 8 != 0) return HICU_ERR_SHAPE;
-  if (a.rs < (p.t.T2 - 1) * a.ps + a.nkb * kblock_of(p.prec)) return HICU_ERR_SHAPE;
-  if (a.nkb * kblock_of(p.prec) < a.k[2] * a.ps) return HICU_ERR_SHAPE;
+  if (a.rs < (t.T2 - 1) * t.D * a.ps + a.nkb * kblock_of(p.prec)) return HICU_ERR_SHAPE;
+  if (a.nkb * kblock_of(p.prec) < (a.k[2] + t.D - 1) * a.ps) return HICU_ERR_SHAPE;
+  if (a.h[2] != t.T2 * t.D + a.k[2] - 1 || a.h[1] != 16 + a.k[1] - 1 || a.h[0] != t.T0 + a.k[0] - 1)
+    return HICU_ERR_SHAPE;
   if ((int64_t)a.ch0 * a.chunk_c < a.chan_base) return HICU_ERR_SHAPE;
+  if (p.lds_bytes > kMaxLds || p.gx * p.gy > 0x7fffffff) return HICU_ERR_SHAPE;
+  const bool pipe = a.nchunks > 1 && conv_can_pipe(p);
+  ConvPlan q = p;
+  q.a.vec = conv_vec(a);
   int32_t s;
-  if (p.prec == P_F32) s = launch_prec<P_F32>(p, st);
-  else if (p.prec == P_BF16) s = launch_prec<P_BF16>(p, st);
-  else s = launch_prec<P_BF16X3>(p, st);
+  if (p.prec == P_F32) s = launch_prec<P_F32>(q, pipe, st);
+  else if (p.prec == P_BF16) s = launch_prec<P_BF16>(q, pipe, st);
+  else s = launch_prec<P_BF16X3>(q, pipe, st);
   if (s != HICU_OK) return s;
   HICU_HIP_TRY(hipGetLastError());
   return HICU_OK;

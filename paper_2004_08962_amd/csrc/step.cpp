@@ -15,18 +15,14 @@ namespace hicu {
 
 
 int32_t plan_forward(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c) {
-  *w = weight_shape(prec, g.k, g.nc, g.nc, 2 * p);
   TuneEntry e;
-  if (tune_lookup(0, prec, g, p, &e) &&
-      plan_conv(prec, TileCfg{e.T0, e.T2, e.WN}, g.k, *w, w->nchunks, g.m, 2 * p, c) == HICU_OK)
-    return HICU_OK;
-  TileCfg t = default_tile(prec, g, 2 * p);
-  int32_t s = plan_conv(prec, t, g.k, *w, w->nchunks, g.m, 2 * p, c);
-  if (s == HICU_ERR_UNSUPPORTED && t.T0 > 1) {
-    t.T0 = 1;
-    t.T2 = 8;
-    s = plan_conv(prec, t, g.k, *w, w->nchunks, g.m, 2 * p, c);
+  if (tune_lookup(0, prec, g, p, &e) && tile_D(e.tile) == 1) {
+    *w = weight_shape(prec, g.k, g.nc, g.nc, 2 * p, 1);
+    if (plan_conv(prec, e.tile, g.k, *w, w->nchunks, g.m, 2 * p, c) == HICU_OK) return HICU_OK;
   }
+  *w = weight_shape(prec, g.k, g.nc, g.nc, 2 * p, 1);
+  int32_t s = plan_conv(prec, default_tile(prec, g, 2 * p, 0), g.k, *w, w->nchunks, g.m, 2 * p, c);
+  if (s == HICU_ERR_UNSUPPORTED) s = plan_conv(prec, 0, g.k, *w, w->nchunks, g.m, 2 * p, c);
   return s;
 }
 
@@ -34,14 +30,14 @@ int32_t plan_adjoint(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c)
   const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
   TuneEntry e;
   if (tune_lookup(1, prec, g, p, &e)) {
-    *w = weight_shape(prec, g.k, p, std::min(e.chunk_c, std::max(1, p)), 2 * g.nc);
-    if (plan_conv(prec, TileCfg{e.T0, e.T2, e.WN}, g.k, *w, w->nchunks, oe, 2 * g.nc, c) == HICU_OK) return HICU_OK;
+    *w = weight_shape(prec, g.k, p, std::min(e.chunk_c, std::max(1, p)), 2 * g.nc, tile_D(e.tile));
+    if (plan_conv(prec, e.tile, g.k, *w, w->nchunks, oe, 2 * g.nc, c) == HICU_OK) return HICU_OK;
   }
   int32_t s = HICU_ERR_UNSUPPORTED;
-  const TileCfg tiles[2] = {default_tile(prec, g, 2 * g.nc), TileCfg{1, 8, default_tile(prec, g, 2 * g.nc).WN}};
-  for (const TileCfg& t : tiles) {
-    for (int cc : {16, 8, 4}) {
-      *w = weight_shape(prec, g.k, p, std::min(cc, std::max(1, p)), 2 * g.nc);
+  const int tiles[2] = {default_tile(prec, g, 2 * g.nc, 1), 0};
+  for (const int t : tiles) {
+    for (int cc : {16, 8, 4, 2, 1}) {
+      *w = weight_shape(prec, g.k, p, std::min(cc, std::max(1, p)), 2 * g.nc, tile_D(t));
       s = plan_conv(prec, t, g.k, *w, w->nchunks, oe, 2 * g.nc, c);
       if (s != HICU_ERR_UNSUPPORTED) return s;
     }
@@ -57,11 +53,11 @@ int filter_group(int64_t s, int p) {
   const size_t per = (size_t)std::max<int64_t>(s, 1) * sizeof(float2);
   const size_t budget = y_budget.load();
   if ((size_t)p * per <= budget) return p;
-  return (int)std::min<size_t>((size_t)p, std::max<size_t>(32, budget / per / 32 * 32));
+  return (int)std::min<size_t>((size_t)p, std::max<size_t>(64, budget / per / 64 * 64));
 }
 
 // Column blocks of the forward launch restricted to filters [c0, c0 + pg).
-static unsigned group_col_blocks(const ConvPlan& c, int pg) { return (unsigned)cdiv(2 * pg, 16 * c.t.WN); }
+static int group_col_blocks(const ConvPlan& c, int pg) { return (int)cdiv(2 * pg, block_cols(c.t)); }
 
 int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* sp) {
   HICU_TRY(plan_forward(g, p, prec, &sp->wf, &sp->cf));
@@ -69,7 +65,7 @@ int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* s
   // Forward partial sums: one per (tile, column block) of every filter group.
   int64_t gy = 0;
   for (int c0 = 0; c0 < p; c0 += sp->pc) gy += group_col_blocks(sp->cf, std::min(sp->pc, p - c0));
-  sp->nf_blocks = (int64_t)sp->cf.grid.x * std::max<int64_t>(gy, sp->cf.grid.y);
+  sp->nf_blocks = sp->cf.gx * std::max<int64_t>(gy, sp->cf.gy);
   sp->na_blocks = 0;
   size_t off = 0;
   sp->off_Y = off;
@@ -81,7 +77,7 @@ int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* s
   sp->off_Ba = sp->off_Balo = off;
   if (need_adj) {
     HICU_TRY(plan_adjoint(g, p, prec, &sp->wa, &sp->ca));
-    sp->na_blocks = (int64_t)sp->ca.grid.x * sp->ca.grid.y;
+    sp->na_blocks = sp->ca.gx * sp->ca.gy;
     sp->off_Ba = off;
     off += al(sp->wa.elems * esize(prec));
     sp->off_Balo = off;
@@ -218,11 +214,11 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     cf.a = sp.cf.a;
     cf.a.col0 = 2 * c0;
     cf.a.coutr = 2 * pg;
-    cf.grid.y = group_col_blocks(cf, pg);
+    cf.gy = group_col_blocks(cf, pg);
     cf.a.os[0] = g.m[1] * g.m[2] * pg;
     cf.a.os[1] = g.m[2] * pg;
     cf.a.os[2] = pg;
-    pf_used += (int64_t)cf.grid.x * cf.grid.y;
+    pf_used += cf.gx * cf.gy;
     {
       ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * pg : 0.0)));
       HICU_TRY(launch_conv(cf, st));

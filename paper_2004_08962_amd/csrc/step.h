@@ -22,7 +22,7 @@ inline size_t esize(int prec) { return prec == P_F32 ? 4 : 2; }
 constexpr size_t kYBudget = size_t(16) << 30;
 
 // Filters per group for s valid outputs and p filters: all of them when Y
-// fits the budget, else the largest multiple of 32 that does (at least 32).
+// fits the budget, else the largest multiple of 64 that does (at least 64).
 int filter_group(int64_t s, int p);
 // Replace the budget (0 restores kYBudget); process-wide.
 void set_y_budget(size_t bytes);

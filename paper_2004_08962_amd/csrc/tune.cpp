@@ -26,8 +26,15 @@ std::string key_of(int role, int prec, const Geo& g, int p) {
   return buf;
 }
 
-const TileCfg kTiles[] = {{1, 8, 1}, {1, 8, 2}, {1, 8, 4}, {1, 4, 1}, {1, 4, 2}, {1, 4, 4},
-                          {2, 4, 1}, {2, 4, 2}, {2, 4, 4}, {2, 8, 1}, {2, 8, 2}, {2, 8, 4}};
+// A shape is a candidate when it fits the problem's dimensionality (T0 > 1
+// only with a kernel extent above 1 on axis 0) and, for D > 1, packs
+// outputs of a kernel with at least 3 taps on axis 2.
+bool candidate(const Geo& g, int tile) {
+  const TileCfg t = tile_cfg(tile);
+  if (g.k[0] == 1 && g.m[0] <= 1 && t.T0 > 1) return false;
+  if (t.D > 1 && g.k[2] < 3) return false;
+  return true;
+}
 
 // Median-free timing: one warm launch, then the mean of `reps` launches.
 int32_t time_plan(const ConvPlan& p, hipStream_t st, float* ms) {
@@ -69,10 +76,12 @@ void tune_store(int role, int prec, const Geo& g, int p, const TuneEntry& e) {
 // the largest partial-sum array over the candidates.
 size_t tune_workspace(const Geo& g, int p, int prec) {
   size_t wmax = 0;
-  for (int cc : {16, 8, 4}) wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc).elems);
-  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p).elems);
+  for (int cc : {16, 8, 4})
+    for (int D : {1, 2, 4})
+      wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc, D).elems);
+  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p, 1).elems);
   const int64_t ext = region_points(g);
-  const int64_t blocks = (int64_t)(cdiv(ext, 16) + 1) * 64 * cdiv(std::max(2 * p, 2 * g.nc), 16);
+  const int64_t blocks = (int64_t)(cdiv(ext, 16) + 1) * 4 * cdiv(std::max(2 * p, 8 * g.nc), 16);
   return al((size_t)g.s * p * sizeof(float2)) + al((size_t)g.npts * g.nc * sizeof(float2)) +
          2 * al(wmax * esize(prec)) + al((size_t)blocks * sizeof(double));
 }
@@ -86,8 +95,10 @@ int32_t autotune(const Geo& g, const void* x, const void* F, int p, int prec, vo
   float2* gbuf = reinterpret_cast<float2*>(at(ws, off));
   off += al((size_t)g.npts * g.nc * sizeof(float2));
   size_t wmax = 0;
-  for (int cc : {16, 8, 4}) wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc).elems);
-  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p).elems);
+  for (int cc : {16, 8, 4})
+    for (int D : {1, 2, 4})
+      wmax = std::max(wmax, weight_shape(prec, g.k, p, std::min(cc, p), 2 * g.nc, D).elems);
+  wmax = std::max(wmax, weight_shape(prec, g.k, g.nc, g.nc, 2 * p, 1).elems);
   void* B = at(ws, off);
   off += al(wmax * esize(prec));
   void* Blo = at(ws, off);
@@ -99,20 +110,20 @@ int32_t autotune(const Geo& g, const void* x, const void* F, int p, int prec, vo
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, false, &sp));
   HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, B, Blo, st));
-  TuneEntry bf{0, 0, 0, g.nc, 1e30f};
-  for (const TileCfg& t : kTiles) {
-    if (g.k[0] == 1 && t.T0 > 1) continue;  // 2-D: no second plane
+  TuneEntry bf{-1, g.nc, 1e30f};
+  for (int tile = 0; tile < kNumTiles; ++tile) {
+    if (!candidate(g, tile) || tile_D(tile) != 1) continue;
     ConvPlan cp;
-    if (plan_conv(prec, t, g.k, sp.wf, sp.wf.nchunks, g.m, 2 * p, &cp) != HICU_OK) continue;
+    if (plan_conv(prec, tile, g.k, sp.wf, sp.wf.nchunks, g.m, 2 * p, &cp) != HICU_OK) continue;
     sp.cf = cp;
     fill_forward_args(g, x, sp, ws, reinterpret_cast<float*>(Y), part);
     sp.cf.a.B = B;
     sp.cf.a.Blo = Blo;
     float ms = 0.f;
     if (time_plan(sp.cf, st, &ms) != HICU_OK) continue;
-    if (ms < bf.ms) bf = TuneEntry{t.T0, t.T2, t.WN, g.nc, ms};
+    if (ms < bf.ms) bf = TuneEntry{tile, g.nc, ms};
   }
-  if (bf.ms >= 1e30f) return HICU_ERR_UNSUPPORTED;
+  if (bf.tile < 0) return HICU_ERR_UNSUPPORTED;
   tune_store(0, prec, g, p, bf);
   // Y from the chosen forward, as the adjoint's input
   HICU_TRY(make_step_plan(g, p, prec, false, &sp));
@@ -123,23 +134,29 @@ int32_t autotune(const Geo& g, const void* x, const void* F, int p, int prec, vo
 
   // adjoint
   const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
-  TuneEntry ba{0, 0, 0, 0, 1e30f};
-  for (int cc : {16, 8, 4}) {
-    const int chunk = std::min(cc, p);
-    const WeightShape wa = weight_shape(prec, g.k, p, chunk, 2 * g.nc);
-    HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, wa, B, Blo, st));
-    for (const TileCfg& t : kTiles) {
-      if (g.k[0] == 1 && t.T0 > 1) continue;
-      ConvPlan cp;
-      if (plan_conv(prec, t, g.k, wa, wa.nchunks, oe, 2 * g.nc, &cp) != HICU_OK) continue;
-      fill_adjoint_args(g, Y, p, B, Blo, gbuf, nullptr, part, cp.a);
-      float ms = 0.f;
-      if (time_plan(cp, st, &ms) != HICU_OK) continue;
-      if (ms < ba.ms) ba = TuneEntry{t.T0, t.T2, t.WN, chunk, ms};
+  TuneEntry ba{-1, 0, 1e30f};
+  for (int D : {1, 2, 4}) {
+    for (int cc : {16, 8, 4}) {
+      const int chunk = std::min(cc, p);
+      const WeightShape wa = weight_shape(prec, g.k, p, chunk, 2 * g.nc, D);
+      bool built = false;
+      for (int tile = 0; tile < kNumTiles; ++tile) {
+        if (!candidate(g, tile) || tile_D(tile) != D) continue;
+        ConvPlan cp;
+        if (plan_conv(prec, tile, g.k, wa, wa.nchunks, oe, 2 * g.nc, &cp) != HICU_OK) continue;
+        if (!built) {
+          HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, wa, B, Blo, st));
+          built = true;
+        }
+        fill_adjoint_args(g, Y, p, B, Blo, gbuf, nullptr, part, cp.a);
+        float ms = 0.f;
+        if (time_plan(cp, st, &ms) != HICU_OK) continue;
+        if (ms < ba.ms) ba = TuneEntry{tile, chunk, ms};
+      }
+      if (chunk < cc) break;
     }
-    if (chunk < cc) break;
   }
-  if (ba.ms >= 1e30f) return HICU_ERR_UNSUPPORTED;
+  if (ba.tile < 0) return HICU_ERR_UNSUPPORTED;
   tune_store(1, prec, g, p, ba);
   if (best_fwd) *best_fwd = bf;
   if (best_adj) *best_adj = ba;
@@ -168,7 +185,7 @@ int32_t hicu_autotune(const hicu_geom* gm, const void* x, const void* F, int32_t
   TuneEntry f, a;
   HICU_TRY(autotune(g, x, F, p, prec, ws, ws_bytes, (hipStream_t)stream, &f, &a));
   if (choice) {
-    const int32_t c[8] = {f.T0, f.T2, f.WN, f.chunk_c, a.T0, a.T2, a.WN, a.chunk_c};
+    const int32_t c[4] = {f.tile, f.chunk_c, a.tile, a.chunk_c};
     std::memcpy(choice, c, sizeof(c));
   }
   return HICU_OK;
@@ -180,8 +197,7 @@ int32_t hicu_tune_save(const char* path) {
   FILE* f = std::fopen(path, "w");
   if (!f) return HICU_ERR_ARG;
   for (const auto& kv : cache)
-    std::fprintf(f, "%s %d %d %d %d %.6f\n", kv.first.c_str(), kv.second.T0, kv.second.T2, kv.second.WN,
-                 kv.second.chunk_c, kv.second.ms);
+    std::fprintf(f, "%s %d %d %.6f\n", kv.first.c_str(), kv.second.tile, kv.second.chunk_c, kv.second.ms);
   std::fclose(f);
   return HICU_OK;
 }
@@ -194,9 +210,8 @@ int32_t hicu_tune_load(const char* path) {
   TuneEntry e;
   int n = 0;
   std::lock_guard<std::mutex> l(mu);
-  while (std::fscanf(f, "%159s %d %d %d %d %f", key, &e.T0, &e.T2, &e.WN, &e.chunk_c, &e.ms) == 6) {
-    const bool ok = (e.T0 == 1 || e.T0 == 2) && (e.T2 == 4 || e.T2 == 8) && e.WN >= 1 && e.WN <= 4 &&
-                    e.WN != 3 && e.chunk_c >= 1;
+  while (std::fscanf(f, "%159s %d %d %f", key, &e.tile, &e.chunk_c, &e.ms) == 4) {
+    const bool ok = e.tile >= 0 && e.tile < kNumTiles && e.chunk_c >= 1;
     if (ok) {
       cache[key] = e;
       ++n;
@@ -206,14 +221,26 @@ int32_t hicu_tune_load(const char* path) {
   return n;
 }
 
-int32_t hicu_tune_put(const hicu_geom* gm, int32_t p, int32_t prec, int32_t role, int32_t T0, int32_t T2, int32_t WN,
-                      int32_t chunk_c) {
+int32_t hicu_tune_put(const hicu_geom* gm, int32_t p, int32_t prec, int32_t role, int32_t tile, int32_t chunk_c) {
   Geo g;
   HICU_TRY(make_geo(gm, &g));
   if (!valid_prec(prec) || role < 0 || role > 1 || p < 1) return HICU_ERR_ARG;
-  if (!((T0 == 1 || T0 == 2) && (T2 == 4 || T2 == 8) && (WN == 1 || WN == 2 || WN == 4) && chunk_c >= 1))
-    return HICU_ERR_ARG;
-  tune_store(role, prec, g, p, TuneEntry{T0, T2, WN, chunk_c, 0.f});
+  if (tile < 0 || tile >= kNumTiles || chunk_c < 1) return HICU_ERR_ARG;
+  if (role == 0 && tile_D(tile) != 1) return HICU_ERR_ARG;
+  tune_store(role, prec, g, p, TuneEntry{tile, chunk_c, 0.f});
+  return HICU_OK;
+}
+
+int32_t hicu_tile_count(void) { return kNumTiles; }
+
+int32_t hicu_tile_info(int32_t tile, int32_t* cfg) {
+  if (tile < 0 || tile >= kNumTiles || !cfg) return HICU_ERR_ARG;
+  const TileCfg t = tile_cfg(tile);
+  cfg[0] = t.T0;
+  cfg[1] = t.T2;
+  cfg[2] = t.WC;
+  cfg[3] = t.FN;
+  cfg[4] = t.D;
   return HICU_OK;
 }
 

@@ -9,7 +9,8 @@
 namespace hicu {
 
 struct TuneEntry {
-  int T0, T2, WN, chunk_c;
+  int tile;     // shape id (conv.h list)
+  int chunk_c;  // adjoint channel chunk
   float ms;
 };
 

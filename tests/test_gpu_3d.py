@@ -67,12 +67,12 @@ def test_grouped_gradient_matches_oracle(hc, case, prec):
     md = _dev(mask) if mask is not None else None
     hc.set_filter_group_budget(0)
     J1, g1, n1 = hc.objective_grad(_dev(x), md, _dev(F), kd, lo, hi, prec=prec)
-    hc.set_filter_group_budget(s * 8 * 32)  # groups of 32 filters and a ragged last group
+    hc.set_filter_group_budget(s * 8 * 64)  # groups of 64 filters and a ragged last group
     try:
         J, g, gn2 = hc.objective_grad(_dev(x), md, _dev(F), kd, lo, hi, prec=prec)
     finally:
         hc.set_filter_group_budget(0)
-    ngroups = -(-p // 32)
+    ngroups = -(-p // 64)
     print(name, prec, "groups", ngroups, flush=True)
     xr, Fr = x.astype(np.complex128), F.astype(np.complex128)
     Jr, gr, _ = oracle.objective_grad(xr, mask, Fr, kd, lo, hi)
