@@ -39,8 +39,8 @@ def _sha(paths):
     return h.hexdigest()[:16]
 
 
-CONV_SOURCES = ["paper_2004_08962_amd/csrc/conv.hip", "paper_2004_08962_amd/csrc/conv.h",
-                "paper_2004_08962_amd/csrc/common.h"]
+CONV_SOURCES = ["paper_2004_08962_amd/csrc/conv_impl.h", "paper_2004_08962_amd/csrc/conv.hip",
+                "paper_2004_08962_amd/csrc/conv.h", "paper_2004_08962_amd/csrc/common.h"]
 
 
 def _traffic(tag, workload, prec):

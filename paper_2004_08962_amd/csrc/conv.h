@@ -94,6 +94,8 @@ struct TileCfg {
 
 constexpr int kNumTiles = 26;
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+// Complex values per thread of the register-pipelined chunk staging.
+constexpr int kStageSlots = 16;
 TileCfg tile_cfg(int id);
 // Block columns of a shape.
 inline int block_cols(const TileCfg& t) { return 16 * t.WC * t.FN; }

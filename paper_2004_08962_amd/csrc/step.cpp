@@ -35,8 +35,12 @@ int32_t plan_adjoint(const Geo& g, int p, int prec, WeightShape* w, ConvPlan* c)
   }
   int32_t s = HICU_ERR_UNSUPPORTED;
   const int tiles[2] = {default_tile(prec, g, 2 * g.nc, 1), 0};
+  // volumes stage 8 channels per chunk (a 6 x 20 x 12 halo), planes 16
+  const int order3[5] = {8, 16, 4, 2, 1}, order2[5] = {16, 8, 4, 2, 1};
+  const int* order = g.k[0] > 1 ? order3 : order2;
   for (const int t : tiles) {
-    for (int cc : {16, 8, 4, 2, 1}) {
+    for (int oi = 0; oi < 5; ++oi) {
+      const int cc = order[oi];
       *w = weight_shape(prec, g.k, p, std::min(cc, std::max(1, p)), 2 * g.nc, tile_D(t));
       s = plan_conv(prec, t, g.k, *w, w->nchunks, oe, 2 * g.nc, c);
       if (s != HICU_ERR_UNSUPPORTED) return s;
