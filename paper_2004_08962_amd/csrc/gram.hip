@@ -77,22 +77,53 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a) {
   const int64_t q_begin = (int64_t)blockIdx.y * a.qper;
   const int64_t q_end = std::min<int64_t>(a.s, q_begin + a.qper);
   const int64_t two_nc = 2 * a.nc;
-  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4) {
-    const int64_t q = q0 + g;
-    double av[2] = {0.0, 0.0}, bv[2] = {0.0, 0.0};
-    if (q < q_end) {
-      const int64_t u2 = q % a.m2, u1 = (q / a.m2) % a.m1, u0 = q / (a.m2 * a.m1);
-      const int64_t base = (((a.lo[0] + u0) * a.d1 + (a.lo[1] + u1)) * a.d2 + (a.lo[2] + u2)) * two_nc;
+  // Lane group g walks positions q_begin + g, + 4, ...: its output index
+  // (u0, u1, u2) and float offset advance incrementally (a carry into u1 /
+  // u0 recomputes the offset), and the operands of the next position are
+  // fetched while the current one multiplies.
+  int64_t q = q_begin + g;
+  int64_t u2 = q % a.m2, u1 = (q / a.m2) % a.m1, u0 = q / (a.m2 * a.m1);
+  auto offset_of = [&]() {
+    return (((a.lo[0] + u0) * a.d1 + (a.lo[1] + u1)) * a.d2 + (a.lo[2] + u2)) * two_nc;
+  };
+  int64_t base = offset_of();
+  auto fetch = [&](double (&av)[2], double (&bv)[2]) {
+    const bool ok = q < q_end;
 #pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        if (okA[f]) av[f] = (double)a.x[base + offA[f]];
-        if (okB[f]) bv[f] = (double)a.x[base + offB[f]];
-      }
+    for (int f = 0; f < 2; ++f) {
+      av[f] = (ok && okA[f]) ? (double)a.x[base + offA[f]] : 0.0;
+      bv[f] = (ok && okB[f]) ? (double)a.x[base + offB[f]] : 0.0;
     }
+    q += 4;
+    u2 += 4;
+    if (u2 < a.m2) {
+      base += 4 * two_nc;
+    } else {
+      while (u2 >= a.m2) {
+        u2 -= a.m2;
+        if (++u1 == a.m1) {
+          u1 = 0;
+          ++u0;
+        }
+      }
+      base = offset_of();
+    }
+  };
+  double av[2], bv[2], an[2], bn[2];
+  fetch(av, bv);
+  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4) {
+    const bool more = q0 + 4 < q_end;
+    if (more) fetch(an, bn);
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[f], bv[j], acc[f][j], 0, 0, 0);
+    if (!more) break;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      av[f] = an[f];
+      bv[f] = bn[f];
+    }
   }
 
   double* out = a.part + ((size_t)blockIdx.y * a.ntri + blockIdx.x) * 4096;
