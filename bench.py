@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HICU gradient iters/s + k-space pts·filters/s, FP32 vs BF16-MFMA at fixed SER"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp16": 2500.0}
+DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3", "fp16": "f16"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -104,19 +105,33 @@ def cpu_baseline(P, steps):
     x = P["x0"].astype(np.complex64).astype(np.complex128)
     kd, r = P["kdims"], P["rank"]
     lo, hi, _ = P["schedule"][0]
+    n = int(np.prod(kd)) * x.shape[3]
+    s_full = int(np.prod([h - l - k + 1 for l, h, k in zip(lo, hi, kd)]))
+    note = ""
+    if s_full * n > 3e7:  # explicit H too large for the host: a centre crop, scaled by valid outputs
+        ext = [h - l for l, h in zip(lo, hi)]
+        crop = [e if k == 1 else min(e, k + 15) for e, k in zip(ext, kd)]
+        lo = tuple(l + (e - c) // 2 for l, e, c in zip(lo, ext, crop))
+        hi = tuple(l + c for l, c in zip(lo, crop))
+        s_crop = int(np.prod([c - k + 1 for c, k in zip(crop, kd)]))
+        note = ", on a %s centre crop of the first region (%d of %d valid outputs), scaled by that ratio" % (
+            "x".join(str(c) for c in crop), s_crop, s_full)
     with ctx:
         threads = ncores
         if threadpool_info is not None:
             threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         t0 = time.perf_counter()
         Q, _, _ = oracle.nullspace(oracle.gram(x, kd, lo, hi), r)
+        F = Q if P["p"] <= 0 else Q @ oracle.jl_matrix(P["seed"], 0, 0, Q.shape[1], P["p"])
         y = x
         for _ in range(steps):
-            y, _, _, _ = oracle.descent_step(y, P["mask"], Q, kd, lo, hi)
+            y, _, _, _ = oracle.descent_step(y, P["mask"], F, kd, lo, hi)
         dt = time.perf_counter() - t0
-    return dict(value=steps / dt, unit="gradient iters/s", cores=int(threads), kind="oracle",
-                sample="1 nullspace update (FP64 Gram + eigh) + %d gradient/ELS steps of the 100-step "
-                       "solve, %.1f s" % (steps, dt))
+    scale = 1.0
+    if note:
+        scale = int(np.prod([h - l - k + 1 for l, h, k in zip(lo, hi, kd)])) / s_full
+    return dict(value=steps / dt * scale, unit="gradient iters/s", cores=int(threads), kind="oracle",
+                sample="1 nullspace update (FP64 Gram + eigh) + %d gradient/ELS steps, %.1f s%s" % (steps, dt, note))
 
 
 def bench_gradient_steps(args, hicu, torch, np, synth):
@@ -178,7 +193,7 @@ def bench_gradient_steps(args, hicu, torch, np, synth):
     line = dict(metric=METRIC, value=round(b["iters_per_s"], 4), unit="gradient iters/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(b["ms_per_step"], 3),
                 higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype={"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}[b["prec"]], data="synthetic",
+                dtype=DTYPE[b["prec"]], data="synthetic",
                 config=dict(workload=args.workload, dims=list(dims), coils=int(P["x0"].shape[3]), kernel=list(kd),
                             rank=r, filters=p, step="one gradient iteration over the full region",
                             filter_group=hicu_filter_group(s_out, p), path=best),
@@ -191,6 +206,76 @@ def bench_gradient_steps(args, hicu, torch, np, synth):
                 roofline=roofline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_volume(P, Q.cpu().numpy(), s_out)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, hicu, torch, np, synth):
+    """Uneven 2-D slices stepped together: a step is one gradient iteration
+    (objective, gradient, line search, update; JL filters drawn per step)
+    of every slice, in one persistent launch per contraction; the timed
+    steps replay a captured HIP graph.  The value counts slice-iterations."""
+    from paper_2004_08962_amd import batch as hb
+    count = 64
+    probs = synth.make_batch2d(count)
+    _progress("generated %d slices" % count)
+    items = []
+    for i, P in enumerate(probs):
+        x0 = torch.from_numpy(P["x0"].astype(np.complex64)).cuda()
+        G = hicu.gram(x0, P["kdims"])
+        Q, _, _, _ = hicu.nullspace(G, P["rank"], want_V=False)
+        items.append(dict(x0=x0, x=x0.clone(), mask=torch.from_numpy(P["mask"]).cuda(), Q=Q, p=P["p"],
+                          kdims=P["kdims"], lo=(0, 0, 0), hi=tuple(P["x0"].shape[:3]), seed=P["seed"]))
+    torch.cuda.synchronize()
+    s_total = sum(int(np.prod([d - k + 1 for d, k in zip(P["x0"].shape[:3], P["kdims"])])) for P in probs)
+    pf_total = sum(int(np.prod([d - k + 1 for d, k in zip(P["x0"].shape[:3], P["kdims"])])) * P["p"] for P in probs)
+    results = {}
+    side = torch.cuda.Stream()
+    for prec in [q.strip() for q in args.paths.split(",") if q.strip()]:
+        for it in items:
+            it["x"].copy_(it["x0"])
+        b = hb.Batch(items, prec=prec)
+        for _ in range(args.warmup):
+            b.step()
+        torch.cuda.synchronize()
+        hicu.profile_begin()
+        for _ in range(args.steps):
+            b.step()
+        torch.cuda.synchronize()
+        prof = hicu.profile_end()
+        b.capture(args.steps, side)
+        torch.cuda.synchronize()
+        b.replay(side)  # warm replay
+        side.synchronize()
+        t0 = time.perf_counter()
+        b.replay(side)
+        side.synchronize()
+        dt = time.perf_counter() - t0
+        results[prec] = dict(prec=prec, seconds=dt, ms_per_step=1e3 * dt / args.steps,
+                             iters_per_s=count * args.steps / dt, prof=prof, info=b.info())
+        b.close()
+        _progress("%s: %.3f ms per batch step" % (prec, 1e3 * dt / args.steps))
+    best = "bf16" if "bf16" in results else next(iter(results))
+    r = results[best]
+    conv = {k: v for k, v in r["prof"].items() if k.startswith("batch_conv") and v["flops"] > 0}
+    dom = max(conv, key=lambda k: conv[k]["total_ms"])
+    d = conv[dom]
+    achieved = d["flops"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[best]
+    line = dict(metric=METRIC, value=round(r["iters_per_s"], 2), unit="slice gradient iters/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(r["ms_per_step"], 4),
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype=DTYPE[best], data="synthetic",
+                config=dict(workload=args.workload, slices=count, valid_outputs=s_total,
+                            step="one gradient iteration of every slice, graph replay", path=best,
+                            tiles=dict(fwd=r["info"]["fwd_tile"], adj=r["info"]["adj_tile"])),
+                pts_filters_per_s=round(pf_total * args.steps / r["seconds"], 1),
+                paths={k: dict(iters_per_s=round(v["iters_per_s"], 2), ms_per_step=round(v["ms_per_step"], 4),
+                               kernel_ms={kk: round(vv["total_ms"] / args.steps, 4) for kk, vv in v["prof"].items()})
+                       for k, v in results.items()},
+                roofline=dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                              frac=round(achieved / peak, 4), traffic=None, kernel=dom,
+                              avg_ms=round(d["avg_ms"], 4), launches=d["launches"],
+                              flops_per_launch=d["flops"] / d["launches"]))
     print(json.dumps(line), flush=True)
 
 
@@ -258,7 +343,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d_256x232x16")
     ap.add_argument("--paths", default=PATHS_DEFAULT,
-                    help="comma list of fp32, bf16x3, bf16+refine")
+                    help="comma list of fp32, bf16x3, bf16+refine, fp16+refine (volumes: fp32, bf16, fp16)")
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -301,6 +386,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "batch2d_64":
+        if args.paths == PATHS_DEFAULT:
+            args.paths = "fp32,bf16"
+        bench_batch(args, hicu, torch, np, synth)
+        return
     if args.workload.startswith("3d_"):
         if args.paths == PATHS_DEFAULT:
             args.paths = "fp32,bf16"
@@ -334,7 +424,7 @@ def main():
         del G, Q
     results = {}
     for path in [q.strip() for q in args.paths.split(",") if q.strip()]:
-        prec, refine = (path, 0) if path != "bf16+refine" else ("bf16", args.refine)
+        prec, refine = (path, 0) if not path.endswith("+refine") else (path.split("+")[0], args.refine)
         for _ in range(args.warmup):
             run(prec, refine)
         torch.cuda.synchronize()
@@ -360,7 +450,7 @@ def main():
     line = dict(metric=METRIC, value=round(b["iters_per_s"], 3), unit="gradient iters/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(b["ms_per_step"], 3),
                 higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype={"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}[b["prec"]],
+                dtype=DTYPE[b["prec"]],
                 data="synthetic",
                 config=dict(workload=args.workload, dims=list(P["x0"].shape[:3]), coils=int(P["x0"].shape[3]),
                             kernel=list(kd), rank=r, filters=p, outer=len(sched), inner=sched[0][2],

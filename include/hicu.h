@@ -52,9 +52,15 @@ typedef enum {
  * FP32; scalar reductions finish in FP64.
  *   HICU_FP32   FP32 operands on the FP32 matrix cores.
  *   HICU_BF16   BF16 operands (round-to-nearest-even), one MFMA per tile.
+ *   HICU_FP16   FP16 operands (round-to-nearest-even).  Each contraction's
+ *               input is first multiplied by a power of two 2^(14 - e),
+ *               e = ceil(log2 max|input|), so the largest magnitude lies
+ *               in [2^13, 2^14] (no overflow at 65504; the scale is exact
+ *               and undone in FP32 after accumulation).  Not available in
+ *               the batched entry points.
  *   HICU_BF16X3 each FP32 operand split into hi + lo BF16 parts, three
  *               MFMAs (hi*hi + hi*lo + lo*hi) per tile: ~16-bit mantissa. */
-typedef enum { HICU_FP32 = 0, HICU_BF16 = 1, HICU_BF16X3 = 2 } hicu_prec;
+typedef enum { HICU_FP32 = 0, HICU_BF16 = 1, HICU_BF16X3 = 2, HICU_FP16 = 3 } hicu_prec;
 
 /* Problem geometry (THEORY section: k-space array, kernel mask, region S).
  * ndim      1..3 spatial axes.  Entries of dims/kdims/lo/hi beyond ndim are

@@ -18,7 +18,7 @@ STATUS = {
     -4: "HICU_ERR_NONFINITE", -5: "HICU_ERR_HIP", -6: "HICU_ERR_WORKSPACE", -7: "HICU_ERR_UNSUPPORTED",
     -8: "HICU_ERR_NOCONV",
 }
-PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3}
 
 
 class Geom(ctypes.Structure):

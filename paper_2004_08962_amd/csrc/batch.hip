@@ -165,6 +165,7 @@ struct hicu_batch_s {
   int64_t total_f = 0, total_a = 0, max_prep_f = 0, max_prep_a = 0, max_n = 0, max_N = 0;
   int max_p = 0, max_nq = 0;
   bool any_zero = false, any_jl = false;
+  double flops = 0.0;  // algorithmic flops of one contraction over all problems (8 n p s each)
   // workspace layout of the shared tables
   size_t off_tables = 0, off_counter = 0, total_bytes = 0;
   size_t t_conv_f = 0, t_conv_a = 0, t_conv_z = 0, t_start_f = 0, t_start_a = 0, t_prep_f = 0, t_prep_a = 0,
@@ -184,6 +185,7 @@ static size_t take(size_t* off, size_t bytes) {
 }
 
 int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch_s* b) {
+  if (prec == P_F16) return HICU_ERR_UNSUPPORTED;  // the batched path scales no operands
   b->count = count;
   b->prec = prec;
   b->items.assign(items, items + count);
@@ -246,6 +248,7 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     b->max_nq = std::max(b->max_nq, P.nq);
     b->any_zero = b->any_zero || !full_region(g);
     b->any_jl = b->any_jl || P.jl;
+    b->flops += 8.0 * g.n * (double)P.p * (double)g.s;
     const size_t es = esize(prec), parts = prec == P_BF16X3 ? 2 : 1;
     P.off_Y = take(&off, (size_t)g.s * P.p * sizeof(float2));
     P.off_Bf = take(&off, sp.wf.elems * es);
@@ -373,7 +376,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
                     reinterpret_cast<const int64_t*>(at(ws, b->t_start_f)), count, b->total_f,
                     (unsigned)std::min<int64_t>(grid, b->total_f), b->lds_f};
   {
-    ProfScope ps("batch_conv_fwd", st);
+    ProfScope ps("batch_conv_fwd", st, b->flops);
     HICU_TRY(launch_conv_batch(f, st));
   }
   hipLaunchKernelGGL(reduce_batch_kernel, dim3(count), dim3(1024), 0, st,
@@ -387,7 +390,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
                     reinterpret_cast<const int64_t*>(at(ws, b->t_start_a)), count, b->total_a,
                     (unsigned)std::min<int64_t>(grid, b->total_a), b->lds_a};
   {
-    ProfScope ps("batch_conv_adj", st);
+    ProfScope ps("batch_conv_adj", st, b->flops);
     HICU_TRY(launch_conv_batch(a, st));
   }
   hipLaunchKernelGGL(reduce_batch_kernel, dim3(count), dim3(1024), 0, st,
@@ -395,7 +398,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
   BatchConvLaunch z = f;
   z.args = reinterpret_cast<const ConvArgs*>(at(ws, b->t_conv_z));
   {
-    ProfScope ps("batch_conv_els", st);
+    ProfScope ps("batch_conv_els", st, b->flops);
     HICU_TRY(launch_conv_batch(z, st));
   }
   hipLaunchKernelGGL(eta_batch_kernel, dim3(count), dim3(1024), 0, st,

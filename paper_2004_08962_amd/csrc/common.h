@@ -43,7 +43,7 @@ int32_t make_geo(const hicu_geom* g, Geo* out);
 // ---------------------------------------------------------------------------
 // Precision modes of the contraction kernels
 // ---------------------------------------------------------------------------
-enum { P_F32 = 0, P_BF16 = 1, P_BF16X3 = 2 };
+enum { P_F32 = 0, P_BF16 = 1, P_BF16X3 = 2, P_F16 = 3 };
 
 // Reduction elements per k-block: FP32 uses four 16x16x4 MFMAs per block of
 // 16, BF16 one 16x16x32 MFMA per block of 32.
@@ -55,6 +55,7 @@ __host__ __device__ constexpr int kblock_of(int prec) { return prec == P_F32 ? 1
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 
 // FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
 __device__ __forceinline__ uint16_t f2bf(float f) {

@@ -46,6 +46,8 @@ struct ConvArgs {
   float scale;
   int accumulate;
   double* partial;        // per-block sum of squares, may be null
+  const float* in_scale;  // FP16: device power of two applied to the staged input (undone in the epilogue)
+  float* absmax;          // per-block max |output|, may be null
 };
 
 // Tile shapes.  A block of 4 waves owns T0 positions along axis 0, 16

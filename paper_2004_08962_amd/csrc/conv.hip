@@ -1,6 +1,6 @@
 // Host side of the contraction kernels (planning, weight builder, launch
 // dispatch); the kernels themselves are in conv_impl.h, instantiated per
-// precision in conv_f32.hip, conv_bf16.hip and conv_bf16x3.hip.
+// precision in conv_f32.hip, conv_bf16.hip, conv_bf16x3.hip and conv_f16.hip.
 #include <algorithm>
 
 #include "conv.h"
@@ -12,6 +12,7 @@ template <int PREC> int32_t launch_batch_prec_impl(const BatchConvLaunch& b, hip
 extern template int32_t launch_prec_impl<P_F32>(const ConvPlan&, bool, hipStream_t);
 extern template int32_t launch_prec_impl<P_BF16>(const ConvPlan&, bool, hipStream_t);
 extern template int32_t launch_prec_impl<P_BF16X3>(const ConvPlan&, bool, hipStream_t);
+extern template int32_t launch_prec_impl<P_F16>(const ConvPlan&, bool, hipStream_t);
 extern template int32_t launch_batch_prec_impl<P_F32>(const BatchConvLaunch&, hipStream_t);
 extern template int32_t launch_batch_prec_impl<P_BF16>(const BatchConvLaunch&, hipStream_t);
 extern template int32_t launch_batch_prec_impl<P_BF16X3>(const BatchConvLaunch&, hipStream_t);
@@ -56,6 +57,8 @@ __device__ __forceinline__ void prep_element(const PrepArgs& a, const int64_t e)
   }
   if (a.prec == P_F32) {
     reinterpret_cast<float*>(a.B)[e] = v;
+  } else if (a.prec == P_F16) {
+    reinterpret_cast<_Float16*>(a.B)[e] = (_Float16)v;
   } else {
     const uint16_t h = f2bf(v);
     reinterpret_cast<uint16_t*>(a.B)[e] = h;
@@ -180,6 +183,7 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
   if (b.nprob < 1 || b.total < 1 || b.grid < 1) return HICU_ERR_ARG;
   if (b.lds_bytes > kMaxLds) return HICU_ERR_UNSUPPORTED;
   int32_t s;
+  if (b.prec == P_F16) return HICU_ERR_UNSUPPORTED;
   if (b.prec == P_F32) s = launch_batch_prec_impl<P_F32>(b, st);
   else if (b.prec == P_BF16) s = launch_batch_prec_impl<P_BF16>(b, st);
   else s = launch_batch_prec_impl<P_BF16X3>(b, st);
@@ -275,7 +279,8 @@ int32_t launch_conv(const ConvPlan& p, hipStream_t st) {
   ConvPlan q = p;
   q.a.vec = conv_vec(a);
   int32_t s;
-  if (p.prec == P_F32) s = launch_prec_impl<P_F32>(q, pipe, st);
+  if (p.prec == P_F16) s = launch_prec_impl<P_F16>(q, pipe, st);
+  else if (p.prec == P_F32) s = launch_prec_impl<P_F32>(q, pipe, st);
   else if (p.prec == P_BF16) s = launch_prec_impl<P_BF16>(q, pipe, st);
   else s = launch_prec_impl<P_BF16X3>(q, pipe, st);
   if (s != HICU_OK) return s;

@@ -1,0 +1,9 @@
+// Instantiations of the contraction kernels for one precision (split from
+// the host code so the precisions compile in parallel).
+#include "conv_impl.h"
+
+namespace hicu {
+
+template int32_t launch_prec_impl<P_F16>(const ConvPlan& p, bool pipe, hipStream_t st);
+
+}  // namespace hicu

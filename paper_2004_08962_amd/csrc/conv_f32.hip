@@ -1,5 +1,5 @@
 // Instantiations of the contraction kernels for one precision (split from
-// the host code so the three precisions compile in parallel).
+// the host code so the precisions compile in parallel).
 #include "conv_impl.h"
 
 namespace hicu {

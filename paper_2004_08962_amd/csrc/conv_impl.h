@@ -23,6 +23,7 @@ namespace hicu {
 template <int PREC> struct LdsElem { using T = float; };
 template <> struct LdsElem<P_BF16> { using T = uint16_t; };
 template <> struct LdsElem<P_BF16X3> { using T = uint16_t; };
+template <> struct LdsElem<P_F16> { using T = uint16_t; };
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -34,6 +35,11 @@ typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{x, y}, bf16x2_t));
 }
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+// Two floats -> packed FP16 (round to nearest even; one v_cvt_pk_f16_f32).
+__device__ __forceinline__ uint32_t pack_f16(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{x, y}, f16x2_t));
+}
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
@@ -41,8 +47,15 @@ __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w 
 // offset off: FP32 as is, BF16 rounded, split BF16 as hi and lo = v - hi.
 template <int PREC, int V>
 __device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typename LdsElem<PREC>::T* lo, int off,
-                                            const float (&v)[2 * V]) {
-  if constexpr (PREC == P_F32) {
+                                            const float (&v)[2 * V], const float sc) {
+  if constexpr (PREC == P_F16) {
+    uint32_t w[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) w[i] = pack_f16(v[2 * i] * sc, v[2 * i + 1] * sc);
+    if constexpr (V == 4) *reinterpret_cast<u32x4_t*>(hi + off) = u32x4_t{w[0], w[1], w[2], w[3]};
+    else if constexpr (V == 2) *reinterpret_cast<u32x2_t*>(hi + off) = u32x2_t{w[0], w[1]};
+    else *reinterpret_cast<uint32_t*>(hi + off) = w[0];
+  } else if constexpr (PREC == P_F32) {
     if constexpr (V == 4) {
       *reinterpret_cast<float4_t*>(hi + off) = float4_t{v[0], v[1], v[2], v[3]};
       *reinterpret_cast<float4_t*>(hi + off + 4) = float4_t{v[4], v[5], v[6], v[7]};
@@ -114,6 +127,9 @@ template <int FM> struct FragA<P_F32, FM> {
 template <int FM> struct FragA<P_BF16X3, FM> {
   bf16x8_t a[FM], al[FM];
 };
+template <int FM> struct FragA<P_F16, FM> {
+  f16x8_t a[FM];
+};
 template <int PREC, int FN> struct FragB {
   bf16x8_t b[FN];
 };
@@ -122,6 +138,9 @@ template <int FN> struct FragB<P_F32, FN> {
 };
 template <int FN> struct FragB<P_BF16X3, FN> {
   bf16x8_t b[FN], bl[FN];
+};
+template <int FN> struct FragB<P_F16, FN> {
+  f16x8_t b[FN];
 };
 
 // Weight prefetch distance in k-steps: a step issues FM * FN MFMAs, so
@@ -138,7 +157,7 @@ template <int FM, int FN> constexpr int prefetch_distance() {
 template <int PREC, int V>
 __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<PREC>::T* lds,
                                             typename LdsElem<PREC>::T* lds_lo, const int cbase, const int64_t base0,
-                                            const int64_t base1, const int64_t base2, const int tid) {
+                                            const int64_t base1, const int64_t base2, const int tid, const float sc) {
   const int cpr = a.chunk_c / V;
   const int ncol = a.h[2] * cpr;
   const int rows = a.h[0] * a.h[1];
@@ -150,7 +169,7 @@ __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<
     const int nv = ok ? max(0, min(V, a.cin - (cbase + cq * V))) : 0;
     float v[2 * V];
     load_unit<V>(a.in, nv ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + coff + cq * V : 0, nv, v);
-    stage_store<PREC, V>(lds, lds_lo, (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V, v);
+    stage_store<PREC, V>(lds, lds_lo, (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V, v, sc);
   };
   if (ncol <= 256) {
     const int R = 256 / ncol;
@@ -201,6 +220,9 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   const int64_t t0i = bx / (a.nt[2] * a.nt[1]);
   const int64_t base0 = t0i * T0, base1 = t1i * 16, base2 = t2i * (T2 * D);
   const int n0w = a.col0 + by * BC + wc * 16 * FN;  // first weight column of this wave
+  // Input scale (a power of two, FP16 only) and its exact inverse for the epilogue.
+  const float in_sc = a.in_scale ? *a.in_scale : 1.f;
+  const float out_sc = a.in_scale ? a.scale / in_sc : a.scale;
 
   // Row tails and the padding of each point past its 2 chunk_c entries are
   // read with zero weights and must hold finite values.
@@ -255,6 +277,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     for (int f = 0; f < FM; ++f) {
       if constexpr (PREC == P_F32) {
         fr.a[f] = *reinterpret_cast<const float4_t*>(lds + frag_off[f] + shift);
+      } else if constexpr (PREC == P_F16) {
+        fr.a[f] = __builtin_bit_cast(f16x8_t, *reinterpret_cast<const u32x4_t*>(lds + frag_off[f] + shift));
       } else {
         fr.a[f] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(lds + frag_off[f] + shift));
         if constexpr (SPLIT)
@@ -270,6 +294,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     for (int j = 0; j < FN; ++j) {
       if constexpr (PREC == P_F32) {
         fr.b[j] = *reinterpret_cast<const float4_t*>(bhi + wlane + j * 16 * KB);
+      } else if constexpr (PREC == P_F16) {
+        fr.b[j] = __builtin_bit_cast(f16x8_t, *reinterpret_cast<const u32x4_t*>(bhi + wlane + j * 16 * KB));
       } else {
         fr.b[j] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(bhi + wlane + j * 16 * KB));
         if constexpr (SPLIT)
@@ -287,6 +313,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
           acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.a[f][1], fb.b[j][1], acc[f][j], 0, 0, 0);
           acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.a[f][2], fb.b[j][2], acc[f][j], 0, 0, 0);
           acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.a[f][3], fb.b[j][3], acc[f][j], 0, 0, 0);
+        } else if constexpr (PREC == P_F16) {
+          acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa.a[f], fb.b[j], acc[f][j], 0, 0, 0);
         } else {
           acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.a[f], fb.b[j], acc[f][j], 0, 0, 0);
           if constexpr (SPLIT) {
@@ -346,9 +374,9 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     for (int ch = 0; ch < a.nchunks; ++ch) {
       const int chg = a.ch0 + ch;
       __syncthreads();
-      if (a.vec == 4) stage_units<PREC, 4>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
-      else if (a.vec == 2) stage_units<PREC, 2>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
-      else stage_units<PREC, 1>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid);
+      if (a.vec == 4) stage_units<PREC, 4>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
+      else if (a.vec == 2) stage_units<PREC, 2>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
+      else stage_units<PREC, 1>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
       __syncthreads();
       compute_chunk(chg);
     }
@@ -397,7 +425,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
       for (int i = 0; i < kStageSlots; ++i)
         if (goff[i] != -2) {
           const float v[2] = {buf[i].x, buf[i].y};
-          stage_store<PREC, 1>(lds, lds_lo, loff[i], v);
+          stage_store<PREC, 1>(lds, lds_lo, loff[i], v, in_sc);
         }
     };
     load(a.ch0);
@@ -419,6 +447,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   // Epilogue: lane holds rows 4g..4g+3 (positions along axis 1) of column m
   // of each of its FM x FN tiles.  Launch column lc = delta * coutr + c.
   double ssq = 0.0;
+  float vmax = 0.f;
 #pragma unroll
   for (int f = 0; f < FM; ++f) {
     const int fg = wr * FM + f;
@@ -439,13 +468,14 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
         if (a.mask)
           masked =
               a.mask[(a.morg[0] + p0) * a.ms[0] + (a.morg[1] + p1) * a.ms[1] + (a.morg[2] + p2) * a.ms[2]] != 0;
-        float v = masked ? 0.f : acc[f][j][i] * a.scale;
+        float v = masked ? 0.f : acc[f][j][i] * out_sc;
         if (a.out) {
           float* dst = a.out + 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]) + c;
           if (a.accumulate) v += *dst;
           *dst = v;
         }
         ssq += (double)v * (double)v;
+        vmax = fmaxf(vmax, fabsf(v));
       }
     }
   }
@@ -453,6 +483,13 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     __shared__ double red[4];
     const double tot = block_sum_d(ssq, red);
     if (tid == 0) a.partial[(size_t)by * gx + bx] = tot;
+  }
+  if (a.absmax) {
+    __shared__ float redm[4];
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+    if (lane == 0) redm[wave] = vmax;
+    __syncthreads();
+    if (tid == 0) a.absmax[(size_t)by * gx + bx] = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
   }
 }
 

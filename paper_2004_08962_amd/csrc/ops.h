@@ -10,4 +10,12 @@ int32_t launch_eta(const double* part, int64_t count, const double* gnorm2, doub
 int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t count, hipStream_t st);
 int32_t launch_zero(void* ptr, size_t bytes, hipStream_t st);
 
+// FP16 operand scaling.  launch_absmax writes per-block maxima of |v| over
+// `count` floats into part (kAbsmaxBlocks entries); launch_scale turns
+// `count` maxima into the power of two 2^(14 - ceil(log2 max)) (1 for a
+// zero or non-finite maximum) at *scale.
+constexpr int kAbsmaxBlocks = 512;
+int32_t launch_absmax(const float* v, int64_t count, float* part, hipStream_t st);
+int32_t launch_scale(const float* part, int64_t count, float* scale, hipStream_t st);
+
 }  // namespace hicu

@@ -143,4 +143,47 @@ int32_t launch_zero(void* ptr, size_t bytes, hipStream_t st) {
   return HICU_OK;
 }
 
+__global__ __launch_bounds__(256) void absmax_kernel(const float* v, int64_t count, float* part) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(v[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+int32_t launch_absmax(const float* v, int64_t count, float* part, hipStream_t st) {
+  hipLaunchKernelGGL(absmax_kernel, dim3(kAbsmaxBlocks), dim3(256), 0, st, v, count, part);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(const float* part, int64_t count, float* scale) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) m = fmaxf(m, part[i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    float s = 1.f;
+    if (m > 0.f && m < INFINITY) {
+      int e;
+      const float f = frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+      const int c = f > 0.5f ? e : e - 1;  // ceil(log2 m)
+      s = ldexpf(1.f, max(-126, min(126, 14 - c)));
+    }
+    *scale = s;
+  }
+}
+
+int32_t launch_scale(const float* part, int64_t count, float* scale, hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(1), dim3(256), 0, st, part, count, scale);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
 }  // namespace hicu

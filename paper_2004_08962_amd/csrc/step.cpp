@@ -93,15 +93,20 @@ int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* s
   off += al(std::max<int64_t>(1, sp->na_blocks) * sizeof(double));
   sp->off_pz = off;
   off += al(sp->nf_blocks * sizeof(double));
+  // FP16 operand scales (x, Y, g) and per-block maxima
+  sp->off_sc = off;
+  off += al(4 * sizeof(float));
+  sp->off_pmax = off;
+  off += al(std::max<int64_t>(kAbsmaxBlocks, sp->nf_blocks) * sizeof(float));
   sp->total = off;
   return HICU_OK;
 }
 
 // Profiler tag of a contraction: kind (0 forward, 1 adjoint, 2 line search) x precision.
 const char* conv_tag(int kind, int prec) {
-  static const char* tags[3][3] = {{"conv_fwd_fp32", "conv_fwd_bf16", "conv_fwd_bf16x3"},
-                                   {"conv_adj_fp32", "conv_adj_bf16", "conv_adj_bf16x3"},
-                                   {"conv_els_fp32", "conv_els_bf16", "conv_els_bf16x3"}};
+  static const char* tags[3][4] = {{"conv_fwd_fp32", "conv_fwd_bf16", "conv_fwd_bf16x3", "conv_fwd_fp16"},
+                                   {"conv_adj_fp32", "conv_adj_bf16", "conv_adj_bf16x3", "conv_adj_fp16"},
+                                   {"conv_els_fp32", "conv_els_bf16", "conv_els_bf16x3", "conv_els_fp16"}};
   return tags[kind][prec];
 }
 
@@ -146,6 +151,8 @@ void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, flo
   a.scale = 1.f;
   a.accumulate = 0;
   a.partial = partial;
+  a.in_scale = nullptr;
+  a.absmax = nullptr;
 }
 
 void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const void* Blo, void* gout,
@@ -178,6 +185,8 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
   a.scale = 2.f;
   a.accumulate = 0;
   a.partial = partial;
+  a.in_scale = nullptr;
+  a.absmax = nullptr;
 }
 
 // Objective, gradient; shared by the public entry and the solver loop.
@@ -200,6 +209,16 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   float2* Y = reinterpret_cast<float2*>(at(ws, sp.off_Y));
   double* pf = reinterpret_cast<double*>(at(ws, sp.off_pf));
   double* pa = reinterpret_cast<double*>(at(ws, sp.off_pa));
+  // FP16: scale of x from its largest magnitude; per group, scale of Y from
+  // the forward's per-block maxima
+  const bool f16 = prec == P_F16;
+  float* scales = reinterpret_cast<float*>(at(ws, sp.off_sc));
+  float* pmax = reinterpret_cast<float*>(at(ws, sp.off_pmax));
+  if (f16) {
+    ProfScope ps("scale", st);
+    HICU_TRY(launch_absmax(reinterpret_cast<const float*>(x), 2 * g.npts * g.nc, pmax, st));
+    HICU_TRY(launch_scale(pmax, kAbsmaxBlocks, scales, st));
+  }
   if (gout) {
     if (!full_region(g)) {
       ProfScope ps("zero", st);
@@ -222,6 +241,11 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     cf.a.os[0] = g.m[1] * g.m[2] * pg;
     cf.a.os[1] = g.m[2] * pg;
     cf.a.os[2] = pg;
+    if (f16) {
+      cf.a.in_scale = scales;
+      if (gout) cf.a.absmax = pmax + pf_used;
+    }
+    const int64_t pmax0 = pf_used;
     pf_used += cf.gx * cf.gy;
     {
       ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * pg : 0.0)));
@@ -235,6 +259,11 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     ca.a.ch0 = c0 / ca.a.chunk_c;
     ca.a.nchunks = (int)cdiv(pg, ca.a.chunk_c);
     ca.a.accumulate = c0 > 0;
+    if (f16) {
+      ProfScope ps("scale", st);
+      HICU_TRY(launch_scale(pmax + pmax0, cf.gx * cf.gy, scales + 1, st));
+      ca.a.in_scale = scales + 1;
+    }
     {
       ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * pg + nS * g.nc * (c0 > 0 ? 2 : 1)) + nS);
       HICU_TRY(launch_conv(ca, st));
@@ -265,6 +294,14 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
   }
   double* pz = reinterpret_cast<double*>(at(ws, sp.off_pz));
   fill_forward_args(g, gv, sp, ws, nullptr, pz);
+  if (prec == P_F16) {
+    ProfScope ps("scale", st);
+    float* scales = reinterpret_cast<float*>(at(ws, sp.off_sc));
+    float* pmax = reinterpret_cast<float*>(at(ws, sp.off_pmax));
+    HICU_TRY(launch_absmax(reinterpret_cast<const float*>(gv), 2 * g.npts * g.nc, pmax, st));
+    HICU_TRY(launch_scale(pmax, kAbsmaxBlocks, scales + 2, st));
+    sp.cf.a.in_scale = scales + 2;
+  }
   {
     ProfScope ps(conv_tag(2, prec), st, 8.0 * g.n * (double)p * (double)g.s, 8.0 * (double)region_points(g) * g.nc);
     HICU_TRY(launch_conv(sp.cf, st));

@@ -12,7 +12,7 @@ constexpr size_t kAlign = 256;
 inline size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
-inline bool valid_prec(int p) { return p == P_F32 || p == P_BF16 || p == P_BF16X3; }
+inline bool valid_prec(int p) { return p == P_F32 || p == P_BF16 || p == P_BF16X3 || p == P_F16; }
 inline size_t esize(int prec) { return prec == P_F32 ? 4 : 2; }
 
 // Bytes of H_S(x)F kept in device memory at once: above this the gradient
@@ -32,7 +32,7 @@ struct StepPlan {
   WeightShape wf, wa;
   ConvPlan cf, ca;      // forward over all filters (also the line search), adjoint
   int pc;               // filters per group of the gradient
-  size_t off_Y, off_Bf, off_Bflo, off_Ba, off_Balo, off_pf, off_pa, off_pz, total;
+  size_t off_Y, off_Bf, off_Bflo, off_Ba, off_Balo, off_pf, off_pa, off_pz, off_sc, off_pmax, total;
   int64_t nf_blocks, na_blocks;
 };
 

@@ -15,12 +15,12 @@ from .phantom import (ellipse_image, ellipsoid_volume, cine_phantom,
                       bandlimited_coil_maps, to_kspace, add_noise)
 from .masks import (vd_lines, line_mask, poisson_disc_2d, volume_mask_from_plane,
                     cine_line_masks)
-from .configs import WORKLOADS, make_problem, co_region, full_region, crop_problem
+from .configs import WORKLOADS, make_problem, make_batch2d, co_region, full_region, crop_problem
 
 __all__ = [
     "ellipse_image", "ellipsoid_volume", "cine_phantom", "gaussian_coil_maps",
     "polynomial_coil_maps", "bandlimited_coil_maps", "to_kspace", "add_noise",
     "vd_lines", "line_mask", "poisson_disc_2d", "volume_mask_from_plane",
     "cine_line_masks", "WORKLOADS", "make_problem", "co_region", "full_region",
-    "crop_problem",
+    "crop_problem", "make_batch2d",
 ]

@@ -16,7 +16,22 @@ U32 = 2.0 ** -24
 # Operand representation error per precision mode: FP32 inputs are exact,
 # BF16 rounds to 8 significant bits, the split hi+lo BF16 pair keeps ~16 bits
 # and drops the lo*lo product.
-U_OP = {"fp32": 0.0, "bf16": 2.0 ** -8, "bf16x3": 3.0 * 2.0 ** -16}
+U_OP = {"fp32": 0.0, "bf16": 2.0 ** -8, "bf16x3": 3.0 * 2.0 ** -16, "fp16": 2.0 ** -11}
+
+# FP16 operands are scaled by 2^(14 - ceil(log2 max|input|)) before
+# rounding; values that land below 2^-14 are subnormal and carry an absolute
+# error up to 2^-25 in scaled units.  The filters are not scaled.
+F16_SUB = 2.0 ** -25
+
+
+def f16_scale(maxabs, margin=1):
+    """Scale the kernels pick for an input of largest magnitude maxabs, one
+    binade smaller when margin=1 (covers a computed maximum slightly above
+    the exact one)."""
+    if maxabs <= 0:
+        return 1.0
+    c = int(np.ceil(np.log2(maxabs)))
+    return 2.0 ** (14 - c - margin)
 
 
 def _ops_factor(prec, terms):
@@ -29,7 +44,13 @@ def forward_bound(x, F, kd, lo, hi, prec):
     n = F.shape[0]
     Y = oracle.forward(x, F, kd, lo, hi)
     Yabs = oracle.forward(np.abs(x), np.abs(F), kd, lo, hi).real
-    return Y, _ops_factor(prec, 2 * n + 2) * Yabs
+    b = _ops_factor(prec, 2 * n + 2) * Yabs
+    if prec == "fp16":
+        sx = f16_scale(float(np.max(np.abs(x))), margin=0)
+        rows = oracle.forward(np.abs(x), np.ones((n, 1)), kd, lo, hi).real  # sum_i |H[u, i]|
+        cols = np.sum(np.abs(F), axis=0)[None, :]                           # sum_i |F[i, j]|
+        b = b + 2.0 * F16_SUB * (cols / sx + rows)
+    return Y, b
 
 
 def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1):
@@ -45,6 +66,13 @@ def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1):
     prop = 2.0 * oracle.hankel_adjoint(eY @ Fa.T, shape, kd, lo, hi).real
     mag = 2.0 * oracle.hankel_adjoint(np.abs(Y) @ Fa.T, shape, kd, lo, hi).real
     b = prop + _ops_factor(prec, 2 * K * p + 2 + groups) * mag
+    if prec == "fp16":
+        n = F.shape[0]
+        sy = f16_scale(float(np.max(np.abs(Y))))
+        ones_s = np.ones((Y.shape[0], p))
+        fsum = oracle.hankel_adjoint(ones_s @ Fa.T, shape, kd, lo, hi).real          # sum over taps, filters of |F|
+        ysum = oracle.hankel_adjoint(np.abs(Y) @ np.ones((p, n)), shape, kd, lo, hi).real  # of |Y|
+        b = b + 2.0 * 2.0 * F16_SUB * (fsum / sy + ysum)
     if mask is not None:
         b[np.asarray(mask).astype(bool)] = 0.0
     return b

@@ -90,7 +90,7 @@ def test_bad_arguments_rejected_before_launch(lib):
 def test_workspace_sizes(lib):
     g = _geom(dims=(1, 256, 232), nc=16)
     s = 252 * 228
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         b = lib.hicu_workspace_bytes(ctypes.byref(g), 280, prec)
         assert b >= s * 280 * 8            # holds the residual Y
         assert b < s * 280 * 8 + (64 << 20)

@@ -55,7 +55,7 @@ GROUP_CASES = [  # (name, shape, kdims, lo, hi, p, use mask)
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp16"])
 @pytest.mark.parametrize("case", GROUP_CASES, ids=[c[0] for c in GROUP_CASES])
 def test_grouped_gradient_matches_oracle(hc, case, prec):
     name, shape, kd, lo, hi, p, use_mask = case

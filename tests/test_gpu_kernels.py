@@ -83,7 +83,7 @@ def test_gram(hc, case):
     assert np.array_equal(G, G.conj().T)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16", "fp16"])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_objective_grad(hc, case, prec):
     name, x, mask, kd, lo, hi = case
@@ -107,7 +107,7 @@ def test_objective_grad(hc, case, prec):
         assert abs(gn2 - gn2r) <= sumsq_bound(gr, eg)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16", "fp16"])
 @pytest.mark.parametrize("case", CASES[:4], ids=IDS[:4])
 def test_line_search_and_update(hc, case, prec):
     name, x, mask, kd, lo, hi = case

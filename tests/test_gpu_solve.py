@@ -51,7 +51,7 @@ def test_solve_fp32_matches_oracle(hc, p64):
         assert np.isfinite(t["J"]) and t["eta"] >= 0
 
 
-@pytest.mark.parametrize("prec,refine,tol_db", [("bf16", 10, 0.1), ("bf16x3", 0, 0.1)])
+@pytest.mark.parametrize("prec,refine,tol_db", [("bf16", 10, 0.1), ("bf16x3", 0, 0.1), ("fp16", 10, 0.1)])
 def test_solve_low_precision_ser(hc, p64, prec, refine, tol_db):
     P, x0, ref = p64
     print("solve", prec, "refine", refine, flush=True)

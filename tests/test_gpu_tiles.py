@@ -35,7 +35,7 @@ def env():
         xr, Fr = x.astype(np.complex128), F.astype(np.complex128)
         Jr, gr, _ = oracle.objective_grad(xr, mask, Fr, kd, lo, hi)
         bounds = {}
-        for prec in ("fp32", "bf16", "bf16x3"):
+        for prec in ("fp32", "bf16", "bf16x3", "fp16"):
             Y, eY = forward_bound(xr, Fr, kd, lo, hi, prec)
             bounds[prec] = (sumsq_bound(Y, eY), grad_bound(xr, mask, Fr, kd, lo, hi, prec))
         out[name] = dict(x=x, mask=mask, F=F, kd=kd, lo=lo, hi=hi, p=p, Jr=Jr, gr=gr, bounds=bounds)
@@ -47,7 +47,7 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp16"])
 @pytest.mark.parametrize("name", ["2d", "3d"])
 def test_every_tile_shape(env, name, prec):
     hicu, hb, torch, probs = env
