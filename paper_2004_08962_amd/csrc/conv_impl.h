@@ -330,7 +330,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   // Weights are fetched PD steps ahead into a ring of NB = PD + 1 register
   // sets, LDS operands one step ahead (double buffered); the loop is
   // unrolled by NB so every ring index is static.
-  constexpr int PD = SPLIT ? (FM * FN >= 16 ? 1 : 3) : prefetch_distance<FM, FN>();
+  constexpr int PD = SPLIT ? 1 : prefetch_distance<FM, FN>();
   constexpr int NB = PD + 1;
   static_assert(NB % 2 == 0, "ring size must be even");
   auto compute_chunk_flat = [&](const int chg) {

@@ -87,21 +87,25 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y * (2.0 - x * y);
 }
 
+// With d = (b - a) / 2 and r = sqrt(d^2 + |c|^2): cos^2 = (1 + |d| / r) / 2,
+// sin = |c| / (2 r cos), signed like d (the smaller rotation, |angle| <=
+// pi/4); the phase of c goes into e.  Three reciprocal square roots, two of
+// them independent, keep the dependent chain short.
 __device__ __forceinline__ bool make_rot_fast(double a, double b, double2 c, double tol, double floor_abs, Rot* r) {
   const double c2 = c.x * c.x + c.y * c.y;
   r->cs = 1.0;
   r->sn = 0.0;
   r->e = make_double2(1.0, 0.0);
   if (!(c2 > tol * tol * fabs(a * b)) || !(c2 > floor_abs * floor_abs)) return false;
-  const double inv = rsqrt_nr(c2);          // 1 / |c|
-  const double zeta = 0.5 * (b - a) * inv;
-  const double az = fabs(zeta);
-  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); for huge |zeta| use 1/(2 zeta)
-  const double t = az > 1e150 ? 0.5 / zeta
-                              : (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + (1.0 + zeta * zeta) * rsqrt_nr(1.0 + zeta * zeta));
-  r->cs = rsqrt_nr(1.0 + t * t);
-  r->sn = t * r->cs;
-  r->e = make_double2(c.x * inv, c.y * inv);
+  const double d = 0.5 * (b - a);
+  const double ir = rsqrt_nr(fma(d, d, c2));  // 1 / r
+  const double ic = rsqrt_nr(c2);             // 1 / |c|
+  const double cs2 = fma(0.5 * fabs(d), ir, 0.5);
+  const double ics = rsqrt_nr(cs2);
+  const double sn = 0.5 * c2 * ic * ir * ics;
+  r->cs = cs2 * ics;
+  r->sn = d >= 0.0 ? sn : -sn;
+  r->e = make_double2(c.x * ic, c.y * ic);
   return true;
 }
 
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
                                                         double tol, const double* floor_dev, double2* Ubuf,
                                                         int* ident) {
   __shared__ double2 S[2][SB][SB + 1];
-  __shared__ double2 U[SB][SB + 1];
+  __shared__ double2 U[2][SB][SB + 1];
   __shared__ Rot rot[SB / 2];
   __shared__ int idx[SB];
   __shared__ int nrot_round, nrot_sweep[MAX_INNER];
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   {
     const int i = tid >> 5, j = tid & 31;
     S[0][i][j] = A[(size_t)idx[i] * npad + idx[j]];
-    U[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    U[0][i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   const double fl = *floor_dev;
   // Early exit when no off-diagonal entry is above the rotation thresholds.
@@ -144,10 +148,13 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
       return;
     }
   }
-  // element owned by this thread: S block (al, be), entry (x, y) of the 2x2
-  const int blk = tid >> 2, al = blk >> 4, be = blk & 15, ex = (tid >> 1) & 1, ey = tid & 1;
-  // U element owned: row ui, pair ub, column (p or q) uc
-  const int ui = tid >> 5, ub = (tid >> 1) & 15, uc = tid & 1;
+  // Threads 0..255 own one 2x2 block (al, be) of S (upper block triangle
+  // only: S is Hermitian, the lower block is written as the mirror);
+  // threads 256..767 own one row of U and one rotation pair (both
+  // columns).  One thread per block reads each entry and rotation once,
+  // which keeps the LDS traffic of a round low.
+  const int al = tid >> 4, be = tid & 15;
+  const int ut = tid - 256, ui = ut >> 4, ub = ut & 15;
   int cur = 0, total = 0;
   for (int sweep = 0; sweep < MAX_INNER; ++sweep) {
     for (int r = 0; r < SB - 1; ++r) {
@@ -168,33 +175,41 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
       }
       __syncthreads();
       if (nrot_round == 0) continue;  // uniform: nothing to rotate this round
-      const Rot ra = rot[al], rb = rot[be];
-      // Element (ex, ey) of Ja^H B Jb with B the 2x2 block of (pair al, pair be):
-      // T_j = a0 B[0][j] + a1 B[1][j], out = b0 T_0 + b1 T_1, where (a0, a1)
-      // is row ex of Ja^H and (b0, b1) column ey of Jb.
-      const double a0 = ex ? ra.sn : ra.cs;
-      const double2 a1 = ex ? csc(ra.cs, ra.e) : csc(-ra.sn, ra.e);
-      const double b0 = ey ? rb.sn : rb.cs;
-      const double2 eb = cconj(rb.e);
-      const double2 b1 = ey ? csc(rb.cs, eb) : csc(-rb.sn, eb);
-      const double2 t0 = cadd(csc(a0, S[cur][ra.p][rb.p]), cmul(a1, S[cur][ra.q][rb.p]));
-      const double2 t1 = cadd(csc(a0, S[cur][ra.p][rb.q]), cmul(a1, S[cur][ra.q][rb.q]));
-      double2 v = cadd(csc(b0, t0), cmul(t1, b1));
-      if (al == be && ra.did) {
-        if (ex != ey) v = make_double2(0.0, 0.0);
-        else v.y = 0.0;
-      }
       const int nx = cur ^ 1;
-      S[nx][ex ? ra.q : ra.p][ey ? rb.q : rb.p] = v;
-      {
+      if (tid < 256) {
+        if (al <= be) {
+          const Rot ra = rot[al], rb = rot[be];
+          double2 b00 = S[cur][ra.p][rb.p], b01 = S[cur][ra.p][rb.q];
+          double2 b10 = S[cur][ra.q][rb.p], b11 = S[cur][ra.q][rb.q];
+          rot2x2(ra, rb, b00, b01, b10, b11);
+          if (al == be) {
+            if (ra.did) {
+              b01 = b10 = make_double2(0.0, 0.0);
+              b00.y = b11.y = 0.0;
+            }
+            S[nx][ra.p][ra.p] = b00;
+            S[nx][ra.p][ra.q] = b01;
+            S[nx][ra.q][ra.p] = b10;
+            S[nx][ra.q][ra.q] = b11;
+          } else {
+            S[nx][ra.p][rb.p] = b00;
+            S[nx][ra.p][rb.q] = b01;
+            S[nx][ra.q][rb.p] = b10;
+            S[nx][ra.q][rb.q] = b11;
+            S[nx][rb.p][ra.p] = cconj(b00);
+            S[nx][rb.q][ra.p] = cconj(b01);
+            S[nx][rb.p][ra.q] = cconj(b10);
+            S[nx][rb.q][ra.q] = cconj(b11);
+          }
+        }
+      } else if (ut < SB * (SB / 2)) {
+        // U <- U J for pair ub: new p = cs up - sn conj(e) uq,
+        //                       new q = sn up + cs conj(e) uq
         const Rot ru = rot[ub];
-        const double2 up = U[ui][ru.p], uq = U[ui][ru.q];
-        const double2 eu = cconj(ru.e);
-        const double c0 = uc ? ru.sn : ru.cs;
-        const double2 c1 = uc ? csc(ru.cs, eu) : csc(-ru.sn, eu);
-        const double2 w = cadd(csc(c0, up), cmul(uq, c1));
-        __syncthreads();  // every U read of this round precedes the writes
-        U[ui][uc ? ru.q : ru.p] = w;
+        const double2 up = U[cur][ui][ru.p], uq = U[cur][ui][ru.q];
+        const double2 w = cmul(uq, cconj(ru.e));
+        U[nx][ui][ru.p] = cadd(csc(ru.cs, up), csc(-ru.sn, w));
+        U[nx][ui][ru.q] = cadd(csc(ru.sn, up), csc(ru.cs, w));
       }
       cur = nx;
     }
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   if (tid == 0) ident[blockIdx.x] = total == 0;
   if (total == 0) return;
   double2* out = Ubuf + (size_t)blockIdx.x * SB * SB;
-  out[tid] = U[tid >> 5][tid & 31];
+  out[tid] = U[cur][tid >> 5][tid & 31];
 }
 
 // Workgroup (alpha, beta): A[ia, ib] <- Ua^H A[ia, ib] Ub and
