@@ -211,14 +211,17 @@ int default_tile(int prec, const Geo& g, int coutr, int role) {
   return is3d ? 13 : 0;
 }
 
+// LDS row stride: a 16-lane row of MFMA operand reads (16 bytes each, one
+// per halo row) is conflict-free when the stride is an odd multiple of 16
+// bytes: 4 mod 8 floats, 8 mod 16 halfwords.
 static int pick_rs(int prec, int need) {
   if (prec == P_F32) {
     int rs = (int)rup(need, 4);
-    while (rs % 64 != 4) rs += 4;
+    while (rs % 8 != 4) rs += 4;
     return rs;
   }
   int rs = (int)rup(need, 8);
-  while (rs % 128 != 8) rs += 8;
+  while (rs % 16 != 8) rs += 8;
   return rs;
 }
 
