@@ -66,8 +66,9 @@ PATHS_DEFAULT = "fp32,bf16x3,bf16+refine"
 def summarize_traffic(paths, kernel_prefix):
     """HBM bytes per dispatch of one kernel from two rocprofv3 --pmc runs
     (paths = [FETCH_SIZE counter_collection.csv, WRITE_SIZE counter_collection.csv]).
-    The plain 256 MiB device copy in the same run (COPY_BYTES read and written)
-    calibrates each counter; kernel_prefix selects the kernel's dispatches by name."""
+    The plain 256 MiB device copy in the same run (COPY_BYTES read and written,
+    the first copy the program dispatches) calibrates each counter;
+    kernel_prefix selects the kernel's dispatches by name."""
     import csv
     vals = {}
     for which, path in zip(("fetch", "write"), paths):
@@ -79,12 +80,12 @@ def summarize_traffic(paths, kernel_prefix):
                 continue
             name = r["Kernel_Name"]
             v = float(r["Counter_Value"])
-            if "elementwise" in name or "copy" in name.lower():
-                copy.append(v)
+            if "copy" in name.lower():
+                copy.append((int(r["Dispatch_Id"]), v))
             elif name.startswith(kernel_prefix):
                 dom.append(v)
-        big = max(copy)  # the 256 MiB calibration copy
-        scale = COPY_BYTES / (big * 1024.0)
+        calib = min(copy)[1]  # the 256 MiB calibration copy comes first
+        scale = COPY_BYTES / (calib * 1024.0)
         vals[which] = (sum(dom) / len(dom) * 1024.0 * scale, scale, len(dom))
     return vals
 
@@ -288,7 +289,7 @@ def hicu_filter_group(s, p):
     per = s * 8
     if p * per <= (16 << 30):
         return p
-    return min(p, max(32, (16 << 30) // per // 32 * 32))
+    return min(p, max(64, (16 << 30) // per // 64 * 64))
 
 
 def cpu_baseline_volume(P, F, s_full):

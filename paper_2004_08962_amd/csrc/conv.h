@@ -48,6 +48,13 @@ struct ConvArgs {
   double* partial;        // per-block sum of squares, may be null
   const float* in_scale;  // FP16: device power of two applied to the staged input (undone in the epilogue)
   float* absmax;          // per-block max |output|, may be null
+  // Compact residual (BF16 operands only): yb = 1 reads the input, yb = 2
+  // writes the output as BF16 (re, im) pairs in blocks of ybw channels,
+  // block b at complex offset b * yblk, points strided by is / os within a
+  // block.  yb = 0: complex64, channels fastest.
+  int yb;
+  int ybw;
+  int64_t yblk;
 };
 
 // Tile shapes.  A block of 4 waves owns T0 positions along axis 0, 16
@@ -92,9 +99,21 @@ struct TileCfg {
   X(22, 2, 8, 1, 4, 4, 1, 0)     \
   X(23, 2, 4, 1, 2, 2, 1, 0)     \
   X(24, 2, 4, 1, 4, 2, 1, 0)     \
-  X(25, 2, 8, 1, 4, 2, 1, 0)
+  X(25, 2, 8, 1, 4, 2, 1, 0)      \
+  X(26, 4, 8, 1, 1, 1, 0, 0)      \
+  X(27, 8, 8, 1, 1, 1, 0, 0)      \
+  X(28, 4, 16, 1, 1, 1, 0, 0)     \
+  X(29, 8, 4, 1, 1, 1, 0, 0)      \
+  X(30, 4, 4, 2, 4, 1, 0, 0)      \
+  X(31, 8, 2, 1, 2, 2, 0, 0)      \
+  X(32, 8, 4, 1, 2, 2, 0, 0)      \
+  X(33, 4, 4, 1, 2, 2, 0, 0)
 
-constexpr int kNumTiles = 26;
+constexpr int kNumTiles = 34;
+// Launch order: weights above kL2Resident bytes are walked one column block
+// at a time over runs of kTileRun position tiles.
+constexpr size_t kL2Resident = 2u << 20;
+constexpr int kTileRun = 32;
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 // Complex values per thread of the register-pipelined chunk staging.
 constexpr int kStageSlots = 16;
@@ -109,6 +128,7 @@ struct ConvPlan {
   ConvArgs a;
   int64_t gx;           // position tiles
   int gy;               // column blocks
+  int run;              // position tiles per run of the launch order (see split_work)
   size_t lds_bytes;
 };
 
@@ -176,6 +196,8 @@ struct BatchConvLaunch {
 int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st);
 // Whether one channel chunk of this plan fits the register staging slots.
 bool conv_can_pipe(const ConvPlan& p);
+// Whether the plan's tile has the compact-residual (yb != 0) variants.
+bool compact_tile_ok(const ConvPlan& p);
 // Widest staging unit the arguments allow: V channels of a point are read
 // with 16-byte loads when the input is 16-byte aligned and the point
 // stride, chunk and channel base are multiples of V.

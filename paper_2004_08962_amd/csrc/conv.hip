@@ -171,6 +171,11 @@ static int64_t stage_elems(const ConvPlan& p) {
 
 bool conv_can_pipe(const ConvPlan& p) { return tile_pipe_ok(p.tile) && stage_elems(p) <= 256 * kStageSlots; }
 
+bool compact_tile_ok(const ConvPlan& p) {
+  const TileCfg t = tile_cfg(p.tile);
+  return p.prec == P_BF16 && t.T0 > 1;
+}
+
 int conv_vec(const ConvArgs& a) {
   const bool aligned = (reinterpret_cast<uintptr_t>(a.in) & 15) == 0;
   for (int V : {4, 2}) {
@@ -197,12 +202,15 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
 // the forward (many columns) takes the 2 x 2 wave grid, the narrow adjoint
 // one or two column fragments per wave without axis-2 packing (the packed
 // shapes lengthen the reduction by (k2 + D - 1) / k2 and were slower once
-// operand fetch stopped being the limit).
+// operand fetch stopped being the limit).  The BF16 volume adjoint, which
+// reads the compact BF16 residual, takes 8 planes x 16 x 4 (timed on a
+// 64 x 320 x 320 x 8 slab with 900 filters: 66.4 ms against 72.6 ms for
+// 2 x 16 x 8).
 int default_tile(int prec, const Geo& g, int coutr, int role) {
   const bool is3d = g.k[0] > 1;
   const int frags = (int)cdiv(coutr, 16);
   if (role == 1) {
-    if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : 16));
+    if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : (prec == P_BF16 ? 29 : 16)));
     return frags >= 3 ? 2 : (frags == 2 ? 1 : 0);
   }
   if (frags >= 8) return is3d ? 19 : (prec == P_F32 ? 6 : (prec == P_BF16X3 ? 2 : 7));
@@ -236,6 +244,9 @@ int32_t plan_conv(int prec, int tile, const int k[3], const WeightShape& ws, int
   plan->t = t;
   a.chunk_c = ws.chunk_c;
   a.chan_base = 0;
+  a.yb = 0;
+  a.ybw = 0;
+  a.yblk = 0;
   a.nchunks = nchunks;
   a.ps = ws.ps;
   a.nkb = ws.nkb;
@@ -261,6 +272,11 @@ int32_t plan_conv(int prec, int tile, const int k[3], const WeightShape& ws, int
   a.coutr = coutr;
   plan->gx = gx;
   plan->gy = (int)gy;
+  // Weights that do not fit comfortably in one XCD's 4 MB L2 next to the
+  // staged inputs are walked one column block at a time over runs of tiles.
+  const size_t wbytes = (size_t)ws.elems * (prec == P_F32 ? 4 : 2) * (prec == P_BF16X3 ? 2 : 1);
+  plan->run = 1;
+  if (gy > 1 && wbytes > kL2Resident) plan->run = (int)std::min<int64_t>(gx, kTileRun);
   return HICU_OK;
 }
 
@@ -278,7 +294,13 @@ int32_t launch_conv(const ConvPlan& p, hipStream_t st) {
     return HICU_ERR_SHAPE;
   if ((int64_t)a.ch0 * a.chunk_c < a.chan_base) return HICU_ERR_SHAPE;
   if (p.lds_bytes > kMaxLds || p.gx * p.gy > 0x7fffffff) return HICU_ERR_SHAPE;
-  const bool pipe = a.nchunks > 1 && conv_can_pipe(p);
+  if (a.yb != 0) {
+    if (!compact_tile_ok(p) || a.ybw < 1 || a.yblk < 0) return HICU_ERR_UNSUPPORTED;
+    if (a.yb == 1 && (a.ybw != a.chunk_c || a.chan_base % a.chunk_c != 0)) return HICU_ERR_SHAPE;
+    if (a.yb == 2 && a.accumulate) return HICU_ERR_UNSUPPORTED;
+    if (a.yb != 1 && a.yb != 2) return HICU_ERR_ARG;
+  }
+  const bool pipe = a.yb == 0 && a.nchunks > 1 && conv_can_pipe(p);
   ConvPlan q = p;
   q.a.vec = conv_vec(a);
   int32_t s;

@@ -157,22 +157,59 @@ template <int FM, int FN> constexpr int prefetch_distance() {
 // by columns (hh2, channel group); when a row of units fits the 256 threads
 // each thread keeps its column (and that column's index arithmetic) and
 // steps over rows, else units are enumerated one by one.
-template <int PREC, int V>
+// V BF16 (re, im) pairs from a compact residual at in + idx (nv < V: one by
+// one, the rest zero), stored to LDS as they are.
+template <int V>
+__device__ __forceinline__ void copy_unit_bf16(const uint32_t* in, int64_t idx, int nv, uint16_t* lds, int off) {
+  uint32_t w[V];
+  if (nv == V) {
+    if constexpr (V == 4) {
+      const u32x4_t t = *reinterpret_cast<const u32x4_t*>(in + idx);
+      w[0] = t[0];
+      w[1] = t[1];
+      w[2] = t[2];
+      w[3] = t[3];
+    } else if constexpr (V == 2) {
+      const u32x2_t t = *reinterpret_cast<const u32x2_t*>(in + idx);
+      w[0] = t[0];
+      w[1] = t[1];
+    } else {
+      w[0] = in[idx];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) w[i] = i < nv ? in[idx + i] : 0u;
+  }
+  if constexpr (V == 4) *reinterpret_cast<u32x4_t*>(lds + off) = u32x4_t{w[0], w[1], w[2], w[3]};
+  else if constexpr (V == 2) *reinterpret_cast<u32x2_t*>(lds + off) = u32x2_t{w[0], w[1]};
+  else *reinterpret_cast<uint32_t*>(lds + off) = w[0];
+}
+
+template <int PREC, int V, bool IB = false>
 __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<PREC>::T* lds,
                                             typename LdsElem<PREC>::T* lds_lo, const int cbase, const int64_t base0,
                                             const int64_t base1, const int64_t base2, const int tid, const float sc) {
   const int cpr = a.chunk_c / V;
   const int ncol = a.h[2] * cpr;
   const int rows = a.h[0] * a.h[1];
-  const int coff = cbase - a.chan_base;
+  // complex64 input: channel offset inside a point; compact BF16 input: the
+  // chunk's block (a chunk is one block)
+  const int64_t coff = IB ? (int64_t)((cbase - a.chan_base) / a.chunk_c) * a.yblk : (int64_t)(cbase - a.chan_base);
   auto unit = [&](const int hh0, const int hh1, const int hh2, const int cq) {
     const int64_t i0 = a.org[0] + base0 + hh0, i1 = a.org[1] + base1 + hh1, i2 = a.org[2] + base2 + hh2;
     const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
                     i2 < a.vhi[2];
     const int nv = ok ? max(0, min(V, a.cin - (cbase + cq * V))) : 0;
-    float v[2 * V];
-    load_unit<V>(a.in, nv ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + coff + cq * V : 0, nv, v);
-    stage_store<PREC, V>(lds, lds_lo, (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V, v, sc);
+    const int64_t idx = nv ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + coff + cq * V : 0;
+    const int off = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V;
+    if constexpr (IB) {
+      static_assert(PREC == P_BF16, "compact residual input is BF16");
+      copy_unit_bf16<V>(reinterpret_cast<const uint32_t*>(a.in), idx, nv, lds, off);
+    } else {
+      float v[2 * V];
+      load_unit<V>(a.in, idx, nv, v);
+      stage_store<PREC, V>(lds, lds_lo, off, v, sc);
+    }
   };
   if (ncol <= 256) {
     const int R = 256 / ncol;
@@ -200,9 +237,10 @@ __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<
 
 // One output tile: position tile bx (of gx) and column block by.  Shared by
 // the per-problem kernel and the persistent batched kernel.
-template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
+template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE, int YB = 0>
 __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, const int by, const int64_t gx,
                                           unsigned char* smem) {
+  static_assert(YB == 0 || (PREC == P_BF16 && !PIPE), "compact residual: BF16, unpipelined");
   constexpr int KB = kblock_of(PREC);
   constexpr int NFRAG = T0 * T2;
   constexpr int WR = 4 / WC;
@@ -435,9 +473,11 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     for (int ch = 0; ch < a.nchunks; ++ch) {
       const int chg = a.ch0 + ch;
       __syncthreads();
-      if (a.vec == 4) stage_units<PREC, 4>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
-      else if (a.vec == 2) stage_units<PREC, 2>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
-      else stage_units<PREC, 1>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
+      constexpr bool IB = YB == 1;
+      if (a.vec == 4) stage_units<PREC, 4, IB>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
+      else if (a.vec == 2)
+        stage_units<PREC, 2, IB>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
+      else stage_units<PREC, 1, IB>(a, lds, lds_lo, chg * a.chunk_c, base0, base1, base2, tid, in_sc);
       __syncthreads();
       compute_chunk(chg);
     }
@@ -531,9 +571,15 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
               a.mask[(a.morg[0] + p0) * a.ms[0] + (a.morg[1] + p1) * a.ms[1] + (a.morg[2] + p2) * a.ms[2]] != 0;
         float v = masked ? 0.f : acc[f][j][i] * out_sc;
         if (a.out) {
-          float* dst = a.out + 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]) + c;
-          if (a.accumulate) v += *dst;
-          *dst = v;
+          if constexpr (YB == 2) {
+            const int f = c >> 1;
+            const int64_t q = (int64_t)(f / a.ybw) * a.yblk + p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2] + f % a.ybw;
+            reinterpret_cast<uint16_t*>(a.out)[2 * q + (c & 1)] = (uint16_t)pack_bf16(v, 0.f);
+          } else {
+            float* dst = a.out + 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]) + c;
+            if (a.accumulate) v += *dst;
+            *dst = v;
+          }
         }
         ssq += (double)v * (double)v;
         vmax = fmaxf(vmax, fabsf(v));
@@ -555,20 +601,36 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin; remap the linear id so
-// that each XCD (own L2) processes a contiguous run of work items: the
-// column blocks of one position tile and neighbouring tiles along axis 2
-// then share staged input through the same L2.
+// that each XCD (own L2) processes a contiguous range of work items, whose
+// neighbours then share staged input and weights through the same L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t W) {
   const int64_t per = W / 8, rem = W % 8;
   const int64_t xcd = w % 8, idx = w / 8;
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, int64_t gx, int gy) {
+// Work item lin -> (position tile, column block).  Tiles go in runs of
+// `run`; inside a run the column blocks are the outer index, so one column
+// block's weights stay in L2 while the run's tiles (whose staged input is
+// also L2-resident) pass through it.  run = 1 is tile-major order.
+__device__ __forceinline__ void split_work(const int64_t lin, const int64_t gx, const int gy, const int run,
+                                           int64_t& tile, int& cb) {
+  const int64_t per = (int64_t)run * gy;
+  const int64_t first = lin / per * run;
+  const int64_t width = min((int64_t)run, gx - first);
+  const int64_t r = lin - first * gy;
+  cb = (int)(r / width);
+  tile = first + (r - (int64_t)cb * width);
+}
+
+template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE, int YB = 0>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, int64_t gx, int gy, int run) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t lin = xcd_remap(blockIdx.x, gx * gy);
-  conv_tile<PREC, T0, T2, WC, FN, D, PIPE>(a, lin / gy, (int)(lin % gy), gx, smem);
+  int64_t tile;
+  int cb;
+  split_work(lin, gx, gy, run, tile, cb);
+  conv_tile<PREC, T0, T2, WC, FN, D, PIPE, YB>(a, tile, cb, gx, smem);
 }
 
 // Persistent batched launch: the work list is every (position tile, column
@@ -602,15 +664,28 @@ int32_t launch_prec_impl(const ConvPlan& p, bool pipe, hipStream_t st) {
   switch (p.tile) {
 #define HICU_TILE_CASE(id, T0, T2, WC, FN, D, P, B)                                                              \
   case id:                                                                                                     \
+    if constexpr (PREC == P_BF16 && T0 > 1) {                                                                  \
+      if (p.a.yb == 1) {                                                                                       \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false, 1>), grid, block, p.lds_bytes, st, p.a, \
+                           p.gx, p.gy, p.run);                                                                 \
+        break;                                                                                                 \
+      }                                                                                                        \
+      if (p.a.yb == 2) {                                                                                       \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false, 2>), grid, block, p.lds_bytes, st, p.a, \
+                           p.gx, p.gy, p.run);                                                                 \
+        break;                                                                                                 \
+      }                                                                                                        \
+    }                                                                                                          \
+    if (p.a.yb != 0) return HICU_ERR_UNSUPPORTED;                                                              \
     if constexpr (P != 0) {                                                                                    \
       if (pipe) {                                                                                              \
         hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, true>), grid, block, p.lds_bytes, st, p.a,     \
-                           p.gx, p.gy);                                                                        \
+                           p.gx, p.gy, p.run);                                                                 \
         break;                                                                                                 \
       }                                                                                                        \
     }                                                                                                          \
     hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false>), grid, block, p.lds_bytes, st, p.a, p.gx,  \
-                       p.gy);                                                                                  \
+                       p.gy, p.run);                                                                           \
     break;
     HICU_TILES(HICU_TILE_CASE)
 #undef HICU_TILE_CASE

@@ -53,8 +53,8 @@ static std::atomic<size_t> y_budget{kYBudget};
 
 void set_y_budget(size_t bytes) { y_budget.store(bytes ? bytes : kYBudget); }
 
-int filter_group(int64_t s, int p) {
-  const size_t per = (size_t)std::max<int64_t>(s, 1) * sizeof(float2);
+int filter_group(int64_t s, int p, size_t bytes) {
+  const size_t per = (size_t)std::max<int64_t>(s, 1) * bytes;
   const size_t budget = y_budget.load();
   if ((size_t)p * per <= budget) return p;
   return (int)std::min<size_t>((size_t)p, std::max<size_t>(64, budget / per / 64 * 64));
@@ -65,7 +65,18 @@ static int group_col_blocks(const ConvPlan& c, int pg) { return (int)cdiv(2 * pg
 
 int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* sp) {
   HICU_TRY(plan_forward(g, p, prec, &sp->wf, &sp->cf));
+  if (need_adj) HICU_TRY(plan_adjoint(g, p, prec, &sp->wa, &sp->ca));
   sp->pc = need_adj ? filter_group(g.s, p) : p;
+  // When Y does not fit at once (filter groups), the BF16 path stores it as
+  // BF16: the adjoint rounds its operand to BF16 anyway, so the stored
+  // values are the ones it would stage, at half the bytes to write and
+  // re-read.  Blocks of the adjoint's chunk width keep every chunk's staging
+  // reads contiguous.
+  sp->ybw = 0;
+  if (need_adj && sp->pc < p && compact_tile_ok(sp->cf) && compact_tile_ok(sp->ca)) {
+    sp->ybw = sp->ca.a.chunk_c;
+    sp->pc = filter_group(g.s, p, sizeof(uint32_t));
+  }
   // Forward partial sums: one per (tile, column block) of every filter group.
   int64_t gy = 0;
   for (int c0 = 0; c0 < p; c0 += sp->pc) gy += group_col_blocks(sp->cf, std::min(sp->pc, p - c0));
@@ -73,14 +84,14 @@ int32_t make_step_plan(const Geo& g, int p, int prec, bool need_adj, StepPlan* s
   sp->na_blocks = 0;
   size_t off = 0;
   sp->off_Y = off;
-  if (need_adj) off += al((size_t)g.s * sp->pc * sizeof(float2));
+  if (need_adj)
+    off += al(sp->ybw ? (size_t)g.s * rup(sp->pc, sp->ybw) * sizeof(uint32_t) : (size_t)g.s * sp->pc * sizeof(float2));
   sp->off_Bf = off;
   off += al(sp->wf.elems * esize(prec));
   sp->off_Bflo = off;
   if (prec == P_BF16X3) off += al(sp->wf.elems * esize(prec));
   sp->off_Ba = sp->off_Balo = off;
   if (need_adj) {
-    HICU_TRY(plan_adjoint(g, p, prec, &sp->wa, &sp->ca));
     sp->na_blocks = sp->ca.gx * sp->ca.gy;
     sp->off_Ba = off;
     off += al(sp->wa.elems * esize(prec));
@@ -228,6 +239,7 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
   }
   int64_t pf_used = 0;
+  const double ybytes = sp.ybw ? 4.0 : 8.0;  // bytes per stored residual value
   for (int c0 = 0; c0 < p; c0 += sp.pc) {
     const int pg = std::min(sp.pc, p - c0);
     const bool last = c0 + pg == p;
@@ -238,9 +250,18 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     cf.a.col0 = 2 * c0;
     cf.a.coutr = 2 * pg;
     cf.gy = group_col_blocks(cf, pg);
-    cf.a.os[0] = g.m[1] * g.m[2] * pg;
-    cf.a.os[1] = g.m[2] * pg;
-    cf.a.os[2] = pg;
+    if (sp.ybw) {  // compact BF16 Y: blocks of ybw filters, points strided by ybw inside a block
+      cf.a.yb = 2;
+      cf.a.ybw = sp.ybw;
+      cf.a.yblk = g.s * sp.ybw;
+      cf.a.os[0] = g.m[1] * g.m[2] * sp.ybw;
+      cf.a.os[1] = g.m[2] * sp.ybw;
+      cf.a.os[2] = sp.ybw;
+    } else {
+      cf.a.os[0] = g.m[1] * g.m[2] * pg;
+      cf.a.os[1] = g.m[2] * pg;
+      cf.a.os[2] = pg;
+    }
     if (f16) {
       cf.a.in_scale = scales;
       if (gout) cf.a.absmax = pmax + pf_used;
@@ -248,7 +269,7 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     const int64_t pmax0 = pf_used;
     pf_used += cf.gx * cf.gy;
     {
-      ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * (nS * g.nc + (gout ? (double)g.s * pg : 0.0)));
+      ProfScope ps(conv_tag(0, prec), st, flops, 8.0 * nS * g.nc + (gout ? ybytes * (double)g.s * pg : 0.0));
       HICU_TRY(launch_conv(cf, st));
     }
     if (!gout) continue;
@@ -259,13 +280,21 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     ca.a.ch0 = c0 / ca.a.chunk_c;
     ca.a.nchunks = (int)cdiv(pg, ca.a.chunk_c);
     ca.a.accumulate = c0 > 0;
+    if (sp.ybw) {
+      ca.a.yb = 1;
+      ca.a.ybw = sp.ybw;
+      ca.a.yblk = g.s * sp.ybw;
+      ca.a.is[0] = g.m[1] * g.m[2] * sp.ybw;
+      ca.a.is[1] = g.m[2] * sp.ybw;
+      ca.a.is[2] = sp.ybw;
+    }
     if (f16) {
       ProfScope ps("scale", st);
       HICU_TRY(launch_scale(pmax + pmax0, cf.gx * cf.gy, scales + 1, st));
       ca.a.in_scale = scales + 1;
     }
     {
-      ProfScope ps(conv_tag(1, prec), st, flops, 8.0 * ((double)g.s * pg + nS * g.nc * (c0 > 0 ? 2 : 1)) + nS);
+      ProfScope ps(conv_tag(1, prec), st, flops, ybytes * (double)g.s * pg + 8.0 * nS * g.nc * (c0 > 0 ? 2 : 1) + nS);
       HICU_TRY(launch_conv(ca, st));
     }
   }

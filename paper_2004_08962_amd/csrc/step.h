@@ -21,9 +21,10 @@ inline size_t esize(int prec) { return prec == P_F32 ? 4 : 2; }
 // with a 5x5x5 kernel) does not fit for hundreds of filters.
 constexpr size_t kYBudget = size_t(16) << 30;
 
-// Filters per group for s valid outputs and p filters: all of them when Y
-// fits the budget, else the largest multiple of 64 that does (at least 64).
-int filter_group(int64_t s, int p);
+// Filters per group for s valid outputs, p filters and `bytes` per stored
+// residual value: all of them when Y fits the budget, else the largest
+// multiple of 64 that does (at least 64).
+int filter_group(int64_t s, int p, size_t bytes = 8);
 // Replace the budget (0 restores kYBudget); process-wide.
 void set_y_budget(size_t bytes);
 
@@ -32,6 +33,7 @@ struct StepPlan {
   WeightShape wf, wa;
   ConvPlan cf, ca;      // forward over all filters (also the line search), adjoint
   int pc;               // filters per group of the gradient
+  int ybw;              // > 0: Y stored as BF16 in blocks of ybw filters (BF16 path, grouped); 0: complex64
   size_t off_Y, off_Bf, off_Bflo, off_Ba, off_Balo, off_pf, off_pa, off_pz, off_sc, off_pmax, total;
   int64_t nf_blocks, na_blocks;
 };
