@@ -203,14 +203,16 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
 // one or two column fragments per wave without axis-2 packing (the packed
 // shapes lengthen the reduction by (k2 + D - 1) / k2 and were slower once
 // operand fetch stopped being the limit).  The BF16 volume adjoint, which
-// reads the compact BF16 residual, takes 8 planes x 16 x 4 (timed on a
-// 64 x 320 x 320 x 8 slab with 900 filters: 66.4 ms against 72.6 ms for
-// 2 x 16 x 8).
+// reads the compact BF16 residual with batched staging loads, takes
+// 8 planes x 16 x 2 pairs packed along axis 2 (D = 2: with 8-channel chunks
+// the widened 6-tap run fills the same three k-blocks as 5 taps), timed on
+// a 64 x 320 x 320 x 8 slab with 900 filters at 62.1 ms, against 66.4 ms for
+// 8 x 16 x 4 unpacked and 76.2 ms for 2 x 16 x 8.
 int default_tile(int prec, const Geo& g, int coutr, int role) {
   const bool is3d = g.k[0] > 1;
   const int frags = (int)cdiv(coutr, 16);
   if (role == 1) {
-    if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : (prec == P_BF16 ? 29 : 16)));
+    if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : (prec == P_BF16 ? 31 : 16)));
     return frags >= 3 ? 2 : (frags == 2 ? 1 : 0);
   }
   if (frags >= 8) return is3d ? 19 : (prec == P_F32 ? 6 : (prec == P_BF16X3 ? 2 : 7));

@@ -152,16 +152,10 @@ template <int FM, int FN> constexpr int prefetch_distance() {
   return FM * FN >= 16 ? 1 : (FM * FN >= 8 ? 3 : 7);
 }
 
-// Stage channels [cbase, cbase + chunk_c) of the halo of one tile into LDS,
-// V channels of one point per unit.  Units form a grid of rows (hh0, hh1)
-// by columns (hh2, channel group); when a row of units fits the 256 threads
-// each thread keeps its column (and that column's index arithmetic) and
-// steps over rows, else units are enumerated one by one.
 // V BF16 (re, im) pairs from a compact residual at in + idx (nv < V: one by
-// one, the rest zero), stored to LDS as they are.
+// one, the rest zero).
 template <int V>
-__device__ __forceinline__ void copy_unit_bf16(const uint32_t* in, int64_t idx, int nv, uint16_t* lds, int off) {
-  uint32_t w[V];
+__device__ __forceinline__ void load_unit_bf16(const uint32_t* in, int64_t idx, int nv, uint32_t (&w)[V]) {
   if (nv == V) {
     if constexpr (V == 4) {
       const u32x4_t t = *reinterpret_cast<const u32x4_t*>(in + idx);
@@ -180,36 +174,54 @@ __device__ __forceinline__ void copy_unit_bf16(const uint32_t* in, int64_t idx, 
 #pragma unroll
     for (int i = 0; i < V; ++i) w[i] = i < nv ? in[idx + i] : 0u;
   }
+}
+
+template <int V>
+__device__ __forceinline__ void store_unit_bf16(uint16_t* lds, int off, const uint32_t (&w)[V]) {
   if constexpr (V == 4) *reinterpret_cast<u32x4_t*>(lds + off) = u32x4_t{w[0], w[1], w[2], w[3]};
   else if constexpr (V == 2) *reinterpret_cast<u32x2_t*>(lds + off) = u32x2_t{w[0], w[1]};
   else *reinterpret_cast<uint32_t*>(lds + off) = w[0];
 }
 
+// Stage channels [cbase, cbase + chunk_c) of the halo of one tile into LDS,
+// V channels of one point per unit.  Units form a grid of rows (hh0, hh1)
+// by columns (hh2, channel group); when a row of units fits the 256 threads
+// each thread keeps its column (and that column's index arithmetic) and
+// steps over rows, else units are enumerated one by one.  IB: the input is
+// a compact BF16 residual, copied as it is; a thread then issues the loads
+// of a batch of units (16 data registers' worth) before their LDS stores,
+// so that many loads are in flight at once.  Complex64 input keeps one unit
+// in flight: batching it raised the register count of the large tiles past
+// the two waves per SIMD they run at.
+
 template <int PREC, int V, bool IB = false>
 __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<PREC>::T* lds,
                                             typename LdsElem<PREC>::T* lds_lo, const int cbase, const int64_t base0,
                                             const int64_t base1, const int64_t base2, const int tid, const float sc) {
+  static_assert(!IB || PREC == P_BF16, "compact residual input is BF16");
   const int cpr = a.chunk_c / V;
   const int ncol = a.h[2] * cpr;
   const int rows = a.h[0] * a.h[1];
   // complex64 input: channel offset inside a point; compact BF16 input: the
   // chunk's block (a chunk is one block)
   const int64_t coff = IB ? (int64_t)((cbase - a.chan_base) / a.chunk_c) * a.yblk : (int64_t)(cbase - a.chan_base);
-  auto unit = [&](const int hh0, const int hh1, const int hh2, const int cq) {
+  constexpr int SB = IB ? 16 / V : 1;
+  float fv[SB][2 * V];
+  uint32_t wv[SB][V];
+  int loff[SB];
+  auto fetch = [&](const int b, const int hh0, const int hh1, const int hh2, const int cq) {
     const int64_t i0 = a.org[0] + base0 + hh0, i1 = a.org[1] + base1 + hh1, i2 = a.org[2] + base2 + hh2;
     const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
                     i2 < a.vhi[2];
     const int nv = ok ? max(0, min(V, a.cin - (cbase + cq * V))) : 0;
     const int64_t idx = nv ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] + coff + cq * V : 0;
-    const int off = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V;
-    if constexpr (IB) {
-      static_assert(PREC == P_BF16, "compact residual input is BF16");
-      copy_unit_bf16<V>(reinterpret_cast<const uint32_t*>(a.in), idx, nv, lds, off);
-    } else {
-      float v[2 * V];
-      load_unit<V>(a.in, idx, nv, v);
-      stage_store<PREC, V>(lds, lds_lo, off, v, sc);
-    }
+    loff[b] = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cq * V;
+    if constexpr (IB) load_unit_bf16<V>(reinterpret_cast<const uint32_t*>(a.in), idx, nv, wv[b]);
+    else load_unit<V>(a.in, idx, nv, fv[b]);
+  };
+  auto put = [&](const int b) {
+    if constexpr (IB) store_unit_bf16<V>(lds, loff[b], wv[b]);
+    else stage_store<PREC, V>(lds, lds_lo, loff[b], fv[b], sc);
   };
   if (ncol <= 256) {
     const int R = 256 / ncol;
@@ -217,20 +229,42 @@ __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<
     if (r0 >= R) return;
     const int hh2 = col / cpr, cq = col - hh2 * cpr;
     int hh0 = r0 / a.h[1], hh1 = r0 - hh0 * a.h[1];
-    for (int row = r0; row < rows; row += R) {
-      unit(hh0, hh1, hh2, cq);
-      hh1 += R;
-      while (hh1 >= a.h[1]) {
-        hh1 -= a.h[1];
-        ++hh0;
+    for (int row = r0; row < rows; row += SB * R) {
+      int nb = 0;
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        if (row + b * R < rows) {
+          fetch(b, hh0, hh1, hh2, cq);
+          nb = b + 1;
+          hh1 += R;
+          while (hh1 >= a.h[1]) {
+            hh1 -= a.h[1];
+            ++hh0;
+          }
+        }
       }
+#pragma unroll
+      for (int b = 0; b < SB; ++b)
+        if (b < nb) put(b);
     }
   } else {
-    for (int e = tid; e < rows * ncol; e += 256) {
-      const int row = e / ncol, col = e - row * ncol;
-      const int hh0 = row / a.h[1], hh1 = row - hh0 * a.h[1];
-      const int hh2 = col / cpr, cq = col - hh2 * cpr;
-      unit(hh0, hh1, hh2, cq);
+    const int total = rows * ncol;
+    for (int e0 = tid; e0 < total; e0 += SB * 256) {
+      int nb = 0;
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        const int e = e0 + b * 256;
+        if (e < total) {
+          const int row = e / ncol, col = e - row * ncol;
+          const int hh0 = row / a.h[1], hh1 = row - hh0 * a.h[1];
+          const int hh2 = col / cpr, cq = col - hh2 * cpr;
+          fetch(b, hh0, hh1, hh2, cq);
+          nb = b + 1;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < SB; ++b)
+        if (b < nb) put(b);
     }
   }
 }
@@ -547,36 +581,49 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
 
   // Epilogue: lane holds rows 4g..4g+3 (positions along axis 1) of column m
   // of each of its FM x FN tiles.  Launch column lc = delta * coutr + c.
+  // Column terms are formed once per column, position terms once per
+  // fragment; the four rows of a fragment step by one position along axis 1.
   double ssq = 0.0;
   float vmax = 0.f;
+  const int64_t r0 = base1 + 4 * g;  // axis-1 position of this lane's first row
+  int cdel[FN];
+  bool cok[FN];
+  int64_t coff[FN];  // column offset in output elements (floats; halfwords for the compact residual)
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int lc = by * BC + (wc * FN + j) * 16 + m;
+    cok[j] = lc < D * a.coutr;
+    cdel[j] = D == 1 ? 0 : lc / a.coutr;
+    const int c = lc - cdel[j] * a.coutr;
+    if constexpr (YB == 2) {
+      const int f = c >> 1;
+      coff[j] = 2 * ((int64_t)(f / a.ybw) * a.yblk + f % a.ybw) + (c & 1);
+    } else {
+      coff[j] = c;
+    }
+  }
 #pragma unroll
   for (int f = 0; f < FM; ++f) {
     const int fg = wr * FM + f;
     const int64_t p0 = base0 + fg / T2, p2b = base2 + (int64_t)(fg % T2) * D;
+    const int64_t obase = p0 * a.os[0] + r0 * a.os[1] + p2b * a.os[2];
+    const int64_t mbase = (a.morg[0] + p0) * a.ms[0] + (a.morg[1] + r0) * a.ms[1] + (a.morg[2] + p2b) * a.ms[2];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int lc = by * BC + (wc * FN + j) * 16 + m;
-      if (lc >= D * a.coutr) continue;
-      const int delta = D == 1 ? 0 : lc / a.coutr;
-      const int c = lc - delta * a.coutr;
-      const int64_t p2 = p2b + delta;
+      if (!cok[j]) continue;
+      if (p0 >= a.oe[0] || p2b + cdel[j] >= a.oe[2]) continue;
+      const int64_t ob = obase + cdel[j] * a.os[2], mb = mbase + cdel[j] * a.ms[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t p1 = base1 + 4 * g + i;
-        const bool pv = p0 < a.oe[0] && p1 < a.oe[1] && p2 < a.oe[2];
-        if (!pv) continue;
-        bool masked = false;
-        if (a.mask)
-          masked =
-              a.mask[(a.morg[0] + p0) * a.ms[0] + (a.morg[1] + p1) * a.ms[1] + (a.morg[2] + p2) * a.ms[2]] != 0;
+        if (r0 + i >= a.oe[1]) continue;
+        const bool masked = a.mask && a.mask[mb + i * a.ms[1]] != 0;
         float v = masked ? 0.f : acc[f][j][i] * out_sc;
         if (a.out) {
+          const int64_t q = ob + i * a.os[1];
           if constexpr (YB == 2) {
-            const int f = c >> 1;
-            const int64_t q = (int64_t)(f / a.ybw) * a.yblk + p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2] + f % a.ybw;
-            reinterpret_cast<uint16_t*>(a.out)[2 * q + (c & 1)] = (uint16_t)pack_bf16(v, 0.f);
+            reinterpret_cast<uint16_t*>(a.out)[2 * q + coff[j]] = (uint16_t)pack_bf16(v, 0.f);
           } else {
-            float* dst = a.out + 2 * (p0 * a.os[0] + p1 * a.os[1] + p2 * a.os[2]) + c;
+            float* dst = a.out + 2 * q + coff[j];
             if (a.accumulate) v += *dst;
             *dst = v;
           }

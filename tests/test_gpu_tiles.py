@@ -73,3 +73,47 @@ def test_every_tile_shape(env, name, prec):
             checked += 1
     hb.tune_clear()
     assert checked >= 20
+
+
+def test_every_volume_tile_compact_residual():
+    """Filter groups on a 3-D problem make the BF16 path store the residual
+    as BF16 in filter blocks (ragged last block) and stage it with batched
+    loads: every shape with several planes, both chunk widths, against the
+    oracle's bounds."""
+    import torch
+    import paper_2004_08962_amd as hicu
+    from paper_2004_08962_amd import batch as hb
+    shape, kd, lo, hi, p = (10, 23, 26, 3), (3, 3, 3), (0, 1, 0), (10, 23, 25), 70
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    mask = (rng.random(shape[:3]) < 0.3).astype(np.uint8)
+    n = kd[0] * kd[1] * kd[2] * shape[3]
+    F = ((rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p))) / np.sqrt(n)).astype(np.complex64)
+    xr, Fr = x.astype(np.complex128), F.astype(np.complex128)
+    Jr, gr, _ = oracle.objective_grad(xr, mask, Fr, kd, lo, hi)
+    Y, eY = forward_bound(xr, Fr, kd, lo, hi, "bf16")
+    bJ = sumsq_bound(Y, eY)
+    bg = grad_bound(xr, mask, Fr, kd, lo, hi, "bf16", groups=2)
+    s = int(np.prod([h - l - k + 1 for l, h, k in zip(lo, hi, kd)]))
+    xd, md, Fd = (torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (x, mask, F))
+    checked = 0
+    hicu.set_filter_group_budget(s * 4 * 64)  # groups of 64 + 6 filters
+    try:
+        for tile in range(hb.tile_count()):
+            T0, T2, WC, FN, D = hb.tile_info(tile)
+            if T0 == 1:
+                continue
+            for chunk in (8, 4):
+                hb.tune_clear()
+                hb.tune_put(shape, kd, p, "bf16", 1, tile, chunk, lo, hi)
+                print("compact residual, tile", tile, (T0, T2, WC, FN, D), "chunk", chunk, flush=True)
+                J, g, gn2 = hicu.objective_grad(xd, md, Fd, kd, lo, hi, prec="bf16")
+                gh = g.cpu().numpy().astype(np.complex128)
+                assert abs(J.item() - Jr) <= bJ, (tile, chunk)
+                assert np.all(np.abs(gh - gr) <= bg + 1e-30), (tile, chunk)
+                assert abs(gn2.item() - float(np.vdot(gh, gh).real)) <= 1e-5 * gn2.item()
+                checked += 1
+    finally:
+        hb.tune_clear()
+        hicu.set_filter_group_budget(0)
+    assert checked >= 30
