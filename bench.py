@@ -355,7 +355,7 @@ def main():
                     help="update profiles/traffic.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--tag", default="conv_adj_bf16")
     ap.add_argument("--prec", default="bf16")
-    ap.add_argument("--kernel", default="void hicu::conv_kernel<1, 1, 8, 1, 2, 1, true>",
+    ap.add_argument("--kernel", default="void hicu::conv_kernel<1, 1, 8, 1, 2, 1, true, 0>",
                     help="name prefix of the dominant kernel's dispatches in the counter CSV")
     args = ap.parse_args()
     if args.summarize_traffic:
