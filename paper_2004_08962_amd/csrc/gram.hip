@@ -16,6 +16,9 @@
 
 namespace hicu {
 
+// Positions (steps of 4) fetched ahead of the MFMAs that use them.
+constexpr int kGramAhead = 8;
+
 struct GramArgs {
   const float* x;       // complex64 array viewed as floats
   int64_t d1, d2;       // array extents of axes 1, 2
@@ -28,7 +31,8 @@ struct GramArgs {
   int ntile;            // 64-wide tiles per dimension
   int ntri;             // upper-triangle tile count
   int64_t qper;         // positions per block (multiple of 4)
-  double* part;         // [gridDim.y][ntri][64][64]
+  int ngroups;          // position ranges
+  double* part;         // [ngroups][ntri][64][64]
 };
 
 __device__ __forceinline__ void tri_index(int t, int ntile, int* I, int* J) {
@@ -50,9 +54,21 @@ __device__ __forceinline__ int64_t real_row_offset(const GramArgs& a, int e) {
   return pt * two_nc + el;
 }
 
+// Work item w of W = ntri * ngroups -> linear item: workgroups reach the 8
+// XCDs round-robin, so the id is remapped to give each XCD a contiguous run
+// of items.  Items are ordered range-major, so the tiles that read the same
+// positions run together and share that XCD's L2.
+__device__ __forceinline__ int64_t gram_remap(int64_t w, int64_t W) {
+  const int64_t per = W / 8, rem = W % 8;
+  const int64_t xcd = w % 8, idx = w / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a) {
+  const int64_t lin = gram_remap(blockIdx.x, (int64_t)a.ntri * a.ngroups);
+  const int tile = (int)(lin % a.ntri), grp = (int)(lin / a.ntri);
   int I, J;
-  tri_index(blockIdx.x, a.ntile, &I, &J);
+  tri_index(tile, a.ntile, &I, &J);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
   const int wr = wave >> 1, wc = wave & 1;
 
@@ -74,25 +90,26 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[f][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t q_begin = (int64_t)blockIdx.y * a.qper;
+  const int64_t q_begin = (int64_t)grp * a.qper;
   const int64_t q_end = std::min<int64_t>(a.s, q_begin + a.qper);
   const int64_t two_nc = 2 * a.nc;
   // Lane group g walks positions q_begin + g, + 4, ...: its output index
   // (u0, u1, u2) and float offset advance incrementally (a carry into u1 /
-  // u0 recomputes the offset), and the operands of the next position are
-  // fetched while the current one multiplies.
+  // u0 recomputes the offset).  Operands are fetched kGramAhead positions
+  // ahead into a register ring and widened to FP64 only when used, so the
+  // loads stay in flight across that many steps of MFMAs.
   int64_t q = q_begin + g;
   int64_t u2 = q % a.m2, u1 = (q / a.m2) % a.m1, u0 = q / (a.m2 * a.m1);
   auto offset_of = [&]() {
     return (((a.lo[0] + u0) * a.d1 + (a.lo[1] + u1)) * a.d2 + (a.lo[2] + u2)) * two_nc;
   };
   int64_t base = offset_of();
-  auto fetch = [&](double (&av)[2], double (&bv)[2]) {
+  auto fetch = [&](float (&av)[2], float (&bv)[2]) {
     const bool ok = q < q_end;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      av[f] = (ok && okA[f]) ? (double)a.x[base + offA[f]] : 0.0;
-      bv[f] = (ok && okB[f]) ? (double)a.x[base + offB[f]] : 0.0;
+      av[f] = (ok && okA[f]) ? a.x[base + offA[f]] : 0.f;
+      bv[f] = (ok && okB[f]) ? a.x[base + offB[f]] : 0.f;
     }
     q += 4;
     u2 += 4;
@@ -109,24 +126,29 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(GramArgs a) {
       base = offset_of();
     }
   };
-  double av[2], bv[2], an[2], bn[2];
-  fetch(av, bv);
-  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4) {
-    const bool more = q0 + 4 < q_end;
-    if (more) fetch(an, bn);
+  constexpr int PF = kGramAhead;
+  float av[PF][2], bv[PF][2];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+  for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[f], bv[j], acc[f][j], 0, 0, 0);
-    if (!more) break;
+    for (int r = 0; r < PF; ++r) {
+      if (q0 + 4 * r >= q_end) break;
+      double ad[2], bd[2];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      av[f] = an[f];
-      bv[f] = bn[f];
+      for (int f = 0; f < 2; ++f) {
+        ad[f] = (double)av[r][f];
+        bd[f] = (double)bv[r][f];
+      }
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[f], bd[j], acc[f][j], 0, 0, 0);
+      fetch(av[r], bv[r]);  // the step PF positions further on
     }
   }
 
-  double* out = a.part + ((size_t)blockIdx.y * a.ntri + blockIdx.x) * 4096;
+  double* out = a.part + ((size_t)grp * a.ntri + tile) * 4096;
 #pragma unroll
   for (int f = 0; f < 2; ++f)
 #pragma unroll
@@ -205,8 +227,10 @@ int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_by
   a.ntile = ntile;
   a.ntri = ntri;
   a.qper = qper;
+  a.ngroups = ngroups;
   a.part = reinterpret_cast<double*>(ws);
-  hipLaunchKernelGGL(gram_tile_kernel, dim3(ntri, ngroups), dim3(256), 0, st, a);
+  if ((int64_t)ntri * ngroups > 0x7fffffff) return HICU_ERR_SHAPE;
+  hipLaunchKernelGGL(gram_tile_kernel, dim3((unsigned)(ntri * ngroups)), dim3(256), 0, st, a);
   HICU_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(gram_finalize_kernel, dim3(ntri), dim3(256), 0, st, (const double*)a.part, ngroups,
                      ntri, ntile, g.n, reinterpret_cast<double2*>(G));
