@@ -370,8 +370,8 @@ def main():
         print(json.dumps(db[("%s/%s/%s" % (args.workload, args.prec, args.tag))]))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); see the sharding notes in the "
-              "design document" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (got --gpus %d); sharding across GPUs is not "
+              "implemented" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

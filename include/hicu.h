@@ -43,7 +43,7 @@ typedef enum {
   HICU_ERR_NONFINITE = -4,     /* a NaN/Inf reached a scalar the loop depends on */
   HICU_ERR_HIP = -5,           /* HIP runtime error */
   HICU_ERR_WORKSPACE = -6,     /* workspace missing or too small */
-  HICU_ERR_UNSUPPORTED = -7,   /* valid request this build does not implement */
+  HICU_ERR_UNSUPPORTED = -7,   /* valid request the library does not implement */
   HICU_ERR_NOCONV = -8         /* eigensolver hit its sweep limit */
 } hicu_status;
 
