@@ -133,6 +133,26 @@ def test_line_search_and_update(hc, case, prec):
     assert np.array_equal(xn[obs], x_before[obs])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape,kd", [((10, 40, 44, 8), (3, 3, 3)), ((1, 60, 70, 8), (1, 5, 5))], ids=["3d", "2d"])
+def test_line_search_many_filters(hc, shape, kd, prec):
+    """1100 filters: the line-search weights exceed 2 MB, so the launch walks
+    column blocks over runs of 32 position tiles (the last run ragged)."""
+    x, mask = _rand_problem(shape, kd, 21)
+    F = _filters(x, kd, None, None, 1100, seed=22)
+    print("line_search many filters", shape, kd, prec, flush=True)
+    xd, Fd = _dev(x), _dev(F)
+    J, g, gn2 = hc.objective_grad(xd, _dev(mask), Fd, kd, prec=prec)
+    eta = hc.line_search(g, gn2, Fd, kd, prec=prec)
+    gh = _host(g).astype(np.complex128)
+    hi = shape[:3]
+    Z, eZ = forward_bound(gh, F.astype(np.complex128), kd, (0, 0, 0), hi, prec)
+    zz = float(np.vdot(Z, Z).real)
+    eta_r = float(gn2.item()) / (2 * zz)
+    rel = sumsq_bound(Z, eZ) / zz
+    assert abs(eta.item() - eta_r) <= (rel / (1 - rel)) * eta_r + 1e-12 * eta_r
+
+
 def test_full_mask_zero_step(hc):
     x, _ = _rand_problem((1, 30, 30, 4), (1, 5, 5), 9)
     full = np.ones((1, 30, 30), np.uint8)
