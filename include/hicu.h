@@ -162,7 +162,10 @@ int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q_dev,
  * When s x p complex values of Y exceed the filter-group budget (16 GiB by
  * default), the filters are processed in groups (a multiple of 64 filters
  * each): Y of one group lives in the workspace and the adjoint of each group
- * is added into g.  J and g are the same sums taken in another order.
+ * is added into g.  J and g are the same sums taken in another order.  On
+ * the BF16 path with tiles of several planes (volumes), a grouped Y is
+ * stored as BF16 (4 bytes per complex value, so groups hold twice the
+ * filters): the adjoint rounds Y to BF16 anyway, so g is unchanged.
  * ------------------------------------------------------------------------ */
 size_t hicu_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
 
