@@ -197,7 +197,8 @@ def bench_gradient_steps(args, hicu, torch, np, synth):
                 dtype=DTYPE[b["prec"]], data="synthetic",
                 config=dict(workload=args.workload, dims=list(dims), coils=int(P["x0"].shape[3]), kernel=list(kd),
                             rank=r, filters=p, step="one gradient iteration over the full region",
-                            filter_group=hicu_filter_group(s_out, p), path=best),
+                            filter_group=hicu.filter_group(x0.shape, kd, p, best, lo, hi)[0],
+                            compact_residual=hicu.filter_group(x0.shape, kd, p, best, lo, hi)[1], path=best),
                 pts_filters_per_s=round(b["iters_per_s"] * s_out * p, 1),
                 setup=dict(gram_s=round(t_gram, 3), nullspace_s=round(t_eig, 3), eig_sweeps=int(sweeps)),
                 paths={k: dict(iters_per_s=round(v["iters_per_s"], 4), ms_per_step=round(v["ms_per_step"], 3),
@@ -282,14 +283,6 @@ def bench_batch(args, hicu, torch, np, synth):
 
 def _progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
-
-
-def hicu_filter_group(s, p):
-    """Filters per group under the default 16 GiB budget for Y (mirrors the library's rule)."""
-    per = s * 8
-    if p * per <= (16 << 30):
-        return p
-    return min(p, max(64, (16 << 30) // per // 64 * 64))
 
 
 def cpu_baseline_volume(P, F, s_full):

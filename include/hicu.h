@@ -174,6 +174,13 @@ size_t hicu_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
  * before a change may be too small after it (calls then return
  * HICU_ERR_WORKSPACE).  Returns HICU_OK. */
 int32_t hicu_set_filter_group_budget(size_t bytes);
+
+/* Filters per group that hicu_objective_grad uses for this geometry, p and
+ * prec under the current budget (*filters = p when Y fits at once), and
+ * whether that Y is the compact BF16 residual (*compact = 1; compact may be
+ * NULL).  Host pointers.  Returns HICU_ERR_ARG / HICU_ERR_SHAPE for bad
+ * arguments, as hicu_objective_grad would. */
+int32_t hicu_filter_group(const hicu_geom* geom, int32_t p, int32_t prec, int32_t* filters, int32_t* compact);
 int32_t hicu_objective_grad(const hicu_geom* geom, const void* x_dev, const uint8_t* mask_dev,
                             const void* F_dev, int32_t p, int32_t prec, double* J_dev,
                             void* g_dev, double* gnorm2_dev, void* ws_dev, size_t ws_bytes,

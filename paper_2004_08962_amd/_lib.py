@@ -69,6 +69,8 @@ SIGNATURES = {
                                    c_uint32, c_void_p, c_void_p, c_void_p]),
     "hicu_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),
     "hicu_set_filter_group_budget": (c_int32, [c_size_t]),
+    "hicu_filter_group": (c_int32, [ctypes.POINTER(Geom), c_int32, c_int32, ctypes.POINTER(c_int32),
+                              ctypes.POINTER(c_int32)]),
     "hicu_objective_grad": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "hicu_line_search": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,

@@ -110,6 +110,14 @@ def set_filter_group_budget(nbytes):
     check(load().hicu_set_filter_group_budget(int(nbytes)), "hicu_set_filter_group_budget")
 
 
+def filter_group(shape, kdims, p, prec="fp32", lo=None, hi=None):
+    """(filters per group of the gradient, whether Y is the compact BF16 residual)."""
+    f, c = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(load().hicu_filter_group(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec), ctypes.byref(f),
+                                   ctypes.byref(c)), "hicu_filter_group")
+    return int(f.value), bool(c.value)
+
+
 def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None):
     return int(load().hicu_workspace_bytes(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec)))
 

@@ -123,6 +123,18 @@ int32_t hicu_set_filter_group_budget(size_t bytes) {
   return HICU_OK;
 }
 
+int32_t hicu_filter_group(const hicu_geom* gm, int32_t p, int32_t prec, int32_t* filters, int32_t* compact) {
+  if (!filters) return HICU_ERR_ARG;
+  Geo g;
+  HICU_TRY(make_geo(gm, &g));
+  if (p < 1 || !valid_prec(prec)) return HICU_ERR_ARG;
+  StepPlan sp;
+  HICU_TRY(make_step_plan(g, p, prec, true, &sp));
+  *filters = sp.pc;
+  if (compact) *compact = sp.ybw > 0;
+  return HICU_OK;
+}
+
 size_t hicu_workspace_bytes(const hicu_geom* gm, int32_t p, int32_t prec) {
   Geo g;
   if (make_geo(gm, &g) != HICU_OK || p < 1 || !valid_prec(prec)) return 0;
