@@ -107,9 +107,11 @@ struct TileCfg {
   X(30, 4, 4, 2, 4, 1, 0, 0)      \
   X(31, 8, 2, 1, 2, 2, 0, 0)      \
   X(32, 8, 4, 1, 2, 2, 0, 0)      \
-  X(33, 4, 4, 1, 2, 2, 0, 0)
+  X(33, 4, 4, 1, 2, 2, 0, 0)      \
+  X(34, 2, 8, 2, 2, 1, 0, 0)      \
+  X(35, 4, 4, 2, 2, 1, 0, 0)
 
-constexpr int kNumTiles = 34;
+constexpr int kNumTiles = 36;
 // Launch order: weights above kL2Resident bytes are walked one column block
 // at a time over runs of kTileRun position tiles.
 constexpr size_t kL2Resident = 2u << 20;

@@ -208,8 +208,11 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
 // the widened 6-tap run fills the same three k-blocks as 5 taps), timed on
 // a 64 x 320 x 320 x 8 slab with 900 filters at 62.1 ms, against 66.4 ms for
 // 8 x 16 x 4 unpacked and 76.2 ms for 2 x 16 x 8.  Its forward, which writes
-// that residual, takes 2 x 16 x 8 positions by 64 columns (53.6 ms against
-// 57.8 ms for 2 x 16 x 4 by 128).
+// that residual, takes 4 x 16 x 4 positions by 64 columns on a 2 x 2 wave
+// grid (8 x 2 fragments per wave: half the weight loads per MFMA of the
+// 4 x 4 register tiles), 49.3 ms against 53.9 ms for 2 x 16 x 8 with one
+// wave column and 57.8 ms for 2 x 16 x 4 by 128; the line search over all
+// filters, which shares the shape, 43.5 against 47.9 ms.
 int default_tile(int prec, const Geo& g, int coutr, int role) {
   const bool is3d = g.k[0] > 1;
   const int frags = (int)cdiv(coutr, 16);
@@ -217,7 +220,7 @@ int default_tile(int prec, const Geo& g, int coutr, int role) {
     if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : (prec == P_BF16 ? 31 : 16)));
     return frags >= 3 ? 2 : (frags == 2 ? 1 : 0);
   }
-  if (frags >= 8) return is3d ? (prec == P_BF16 ? 18 : 19) : (prec == P_F32 ? 6 : (prec == P_BF16X3 ? 2 : 7));
+  if (frags >= 8) return is3d ? (prec == P_BF16 ? 35 : 19) : (prec == P_F32 ? 6 : (prec == P_BF16X3 ? 2 : 7));
   if (frags >= 3) return is3d ? 15 : 2;
   if (frags == 2) return is3d ? 14 : 1;
   return is3d ? 13 : 0;
