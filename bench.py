@@ -281,6 +281,50 @@ def bench_batch(args, hicu, torch, np, synth):
     print(json.dumps(line), flush=True)
 
 
+def bench_ablation(args, hicu, torch, np, synth):
+    """JL filter count x centre-out schedule on the 256 x 232 x 16 workload
+    (the paper's study of its two acceleration techniques): full
+    reconstructions, 20 outer x 5 inner iterations on the bf16+refine path,
+    with p JL filters drawn per step (p = 0: all 280 nullspace filters) and
+    the first `co` outer iterations on the centre box (a quarter of each
+    in-plane axis).  Prints one JSON line with a row per configuration."""
+    from synth.configs import co_region, full_region
+    P = synth.make_problem("2d_256x232x16")
+    kd, r = P["kdims"], P["rank"]
+    x0 = torch.from_numpy(P["x0"].astype(np.complex64)).cuda()
+    mask = torch.from_numpy(P["mask"]).cuda()
+    x_true = P["x_true"]
+    dims = P["x0"].shape[:3]
+    full, co = full_region(dims), co_region(dims, kd, (1, 2))
+    nq = hicu.num_taps(x0.shape, kd) - r
+
+    def ser(x):
+        xh = x.cpu().numpy().astype(np.complex128)
+        return float(20 * np.log10(np.linalg.norm(x_true) / np.linalg.norm(xh - x_true)))
+
+    rows = []
+    for p in (0, 64, 32, 16, 8):
+        for co_outer in (0, 10):
+            sched = [((co if i < co_outer else full)[0], (co if i < co_outer else full)[1], 5) for i in range(20)]
+
+            def run():
+                return hicu.solve(x0, mask, kd, r, sched, p=p, seed=P["seed"], prec="bf16", refine_steps=10)
+
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                x, trace = run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            rows.append(dict(filters=p if p else nq, jl=p > 0, co_outer=co_outer, ms_per_solve=round(1e3 * dt, 2),
+                             iters_per_s=round(100 / dt, 2), ser_db=round(ser(x), 4), final_J=trace[-1]["J"]))
+            _progress("p=%d co=%d: %.1f ms, SER %.3f dB" % (p, co_outer, 1e3 * dt, rows[-1]["ser_db"]))
+    print(json.dumps(dict(ablation="jl_filters_x_centre_out", workload="2d_256x232x16", path="bf16+refine",
+                          data="synthetic", steps=args.steps, warmup=args.warmup, rows=rows)), flush=True)
+
+
 def _progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
@@ -344,6 +388,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--autotune", action="store_true", help="tune tile shapes on the workload before timing")
+    ap.add_argument("--ablation", action="store_true",
+                    help="JL filter count x centre-out schedule on the 2-D workload (one JSON line of rows)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="update profiles/traffic.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--tag", default="conv_adj_bf16")
@@ -380,6 +426,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.ablation:
+        bench_ablation(args, hicu, torch, np, synth)
+        return
     if args.workload == "batch2d_64":
         if args.paths == PATHS_DEFAULT:
             args.paths = "fp32,bf16"
