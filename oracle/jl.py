@@ -18,8 +18,11 @@ definitions):
   z0 = R cos(2 pi u1), z1 = R sin(2 pi u1) with R = sqrt(-2 ln u0), and
   likewise z2, z3 from (u2, u3).  P[e] = z[e mod 4] / sqrt(p).
 
-Parity: pinned statistically (moments, normality, unbiasedness of
-E[Q P P^T Q'] = Q Q'); the bit stream is compared GPU-vs-oracle.
+Parity: the block function is pinned bit for bit against rocRAND's
+independent Philox4x32-10 (ROCm's source header compiled for the host) on
+structured and random counters and keys, together with the counter layout
+above; the normals are pinned statistically (moments, normality,
+unbiasedness of E[Q P P^T Q'] = Q Q').
 """
 import numpy as np
 
