@@ -198,7 +198,9 @@ int32_t hicu_line_search(const hicu_geom* geom, const void* g_dev, const double*
 
 /* x <- x - eta g over the whole array (Algorithm 1 update); eta read from
  * device memory.  Observed entries stay bit-identical because g is zero
- * there. */
+ * there.  A zero or non-finite eta leaves x untouched (hicu_line_search
+ * returns eta = 0 when any scalar it reads is non-finite, so a poisoned
+ * gradient never reaches x). */
 int32_t hicu_update(const hicu_geom* geom, void* x_dev, const void* g_dev,
                     const double* eta_dev, void* stream);
 
@@ -233,10 +235,20 @@ typedef struct {
  * x0_dev    complex64 zero-filled observations (full array).
  * mask_dev  uint8 observed mask (may be NULL).
  * x_out_dev complex64 result; may alias x0_dev.
- * Allocates its own device workspace for the call.  Synchronous. */
+ * ws_dev    device workspace of at least hicu_solve_workspace_bytes(geom,
+ *           params) bytes (0 for invalid arguments); the call allocates
+ *           nothing.
+ * Synchronous (it reads the step scalars once per outer iteration).
+ * Non-finite values: an x0 holding NaN/Inf is rejected with
+ * HICU_ERR_NONFINITE before anything is written.  If a J, ||g||^2 or eta
+ * turns non-finite during the run, the steps from there on are zero steps,
+ * the run stops after that outer iteration with HICU_ERR_NONFINITE, and
+ * x_out holds the last finite iterate; trace records of steps not run have
+ * outer = inner = prec = -1. */
+size_t hicu_solve_workspace_bytes(const hicu_geom* geom, const hicu_params* params);
 int32_t hicu_solve(const hicu_geom* geom, const void* x0_dev, const uint8_t* mask_dev,
                    const hicu_params* params, void* x_out_dev, hicu_trace* trace_host,
-                   void* stream);
+                   void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched gradient steps (Algorithm 1 gradient, ELS and update steps for many
@@ -336,7 +348,8 @@ int32_t hicu_tile_info(int32_t tile, int32_t* cfg);
  * max_stats; *n_stats receives the number of classes).  flops/bytes are the
  * algorithmic work summed over the class's launches (the convolutions count
  * 8 n p s real flops each: one complex multiply-add per tap, filter and
- * output).  Process-wide; not meant for concurrent use from several threads.
+ * output; the Gram 4 s n^2, the count of a Hermitian product H'H).
+ * Process-wide; not meant for concurrent use from several threads.
  * ------------------------------------------------------------------------ */
 typedef struct {
   char name[24];

@@ -8,9 +8,10 @@ gradient steps and exact line search on ||H(x) Q||_F^2 (Algorithm 1).
 from ._lib import HicuError, load, LIB_PATH
 from .api import (geom, num_taps, gram, nullspace, jl_compress, workspace_bytes, set_filter_group_budget, filter_group,
                   objective_grad,
-                  line_search, update, solve, profile_begin, profile_end)
+                  line_search, update, solve, solve_workspace_bytes, profile_begin, profile_end)
 
 __all__ = ["HicuError", "load", "LIB_PATH", "geom", "num_taps", "gram", "nullspace", "jl_compress",
            "set_filter_group_budget", "filter_group",
-           "workspace_bytes", "objective_grad", "line_search", "update", "solve", "profile_begin",
+           "workspace_bytes", "objective_grad", "line_search", "update", "solve", "solve_workspace_bytes",
+           "profile_begin",
            "profile_end"]

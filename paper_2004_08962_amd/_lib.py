@@ -96,8 +96,9 @@ SIGNATURES = {
     "hicu_tune_put": (c_int32, [ctypes.POINTER(Geom), c_int32, c_int32, c_int32, c_int32, c_int32]),
     "hicu_tile_count": (c_int32, []),
     "hicu_tile_info": (c_int32, [c_int32, c_void_p]),
+    "hicu_solve_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), ctypes.POINTER(Params)]),
     "hicu_solve": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, ctypes.POINTER(Params), c_void_p,
-                             ctypes.POINTER(Trace), c_void_p]),
+                             ctypes.POINTER(Trace), c_void_p, c_size_t, c_void_p]),
 }
 
 _LIB = None

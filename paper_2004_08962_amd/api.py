@@ -30,6 +30,26 @@ def _dev(t, dtype, name):
     return t
 
 
+def _shape_checks(x_shape=None, kdims=None, F=None, mask=None, like=None, like_name="g"):
+    """Shape agreement between the arguments, checked before any device
+    pointer is handed to the library (a mismatched buffer would be read or
+    written out of bounds by the kernels)."""
+    if x_shape is not None and len(x_shape) != 4:
+        raise ValueError("k-space must have shape (D0, D1, D2, Nc), got %s" % (tuple(x_shape),))
+    if F is not None:
+        if F.dim() != 2:
+            raise ValueError("F must be 2-D (n, p), got %s" % (tuple(F.shape),))
+        if x_shape is not None and kdims is not None:
+            n = int(kdims[0]) * int(kdims[1]) * int(kdims[2]) * int(x_shape[3])
+            if F.shape[0] != n:
+                raise ValueError("F has %d rows; the kernel %s over %d coils has %d taps"
+                                 % (F.shape[0], tuple(kdims), int(x_shape[3]), n))
+    if mask is not None and x_shape is not None and tuple(mask.shape) != tuple(x_shape[:3]):
+        raise ValueError("mask shape %s does not match k-space %s" % (tuple(mask.shape), tuple(x_shape[:3])))
+    if like is not None and x_shape is not None and tuple(like.shape) != tuple(x_shape):
+        raise ValueError("%s shape %s does not match x %s" % (like_name, tuple(like.shape), tuple(x_shape)))
+
+
 def geom(shape, kdims, lo=None, hi=None):
     """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box."""
     d = [int(v) for v in shape[:3]]
@@ -62,6 +82,7 @@ def num_taps(shape, kdims):
 
 def gram(x, kdims, lo=None, hi=None):
     """G = H_S(x)' H_S(x) as complex128 (n, n)."""
+    _shape_checks(x.shape)
     lib = load()
     _dev(x, torch.complex64, "x")
     g = geom(x.shape, kdims, lo, hi)
@@ -76,9 +97,15 @@ def gram(x, kdims, lo=None, hi=None):
 
 def nullspace(G, rank, V0=None, want_V=True):
     """Returns (Q complex64 (n, n-r), evals float64 (n,), V complex128 or None, sweeps)."""
+    if G.dim() != 2 or G.shape[0] != G.shape[1]:
+        raise ValueError("G must be square, got %s" % (tuple(G.shape),))
+    n = G.shape[0]
+    if V0 is not None and tuple(V0.shape) != (n, n):
+        raise ValueError("V0 must be %d x %d, got %s" % (n, n, tuple(V0.shape)))
+    if not 0 <= int(rank) < n:
+        raise ValueError("rank %d outside [0, %d)" % (int(rank), n))
     lib = load()
     _dev(G, torch.complex128, "G")
-    n = G.shape[0]
     if V0 is not None:
         _dev(V0, torch.complex128, "V0")
     Q = torch.empty((n, n - rank), dtype=torch.complex64, device=G.device)
@@ -94,6 +121,8 @@ def nullspace(G, rank, V0=None, want_V=True):
 
 def jl_compress(Q, p, seed, outer, inner, stream_id=0, return_P=False):
     """F = Q P with P drawn on the device (Philox4x32-10 + Box-Muller)."""
+    if Q.dim() != 2:
+        raise ValueError("Q must be 2-D (n, nq), got %s" % (tuple(Q.shape),))
     lib = load()
     _dev(Q, torch.complex64, "Q")
     n, nq = Q.shape
@@ -125,6 +154,7 @@ def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None):
 def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=True, ws=None):
     """Returns (J, g, gnorm2): J and gnorm2 are 0-dim float64 CUDA tensors,
     g complex64 like x (None when want_grad is False)."""
+    _shape_checks(x.shape, kdims, F, mask)
     lib = load()
     _dev(x, torch.complex64, "x")
     _dev(F, torch.complex64, "F")
@@ -146,6 +176,9 @@ def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=T
 
 def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None):
     """eta = ||g||^2 / (2 ||H(g) F||^2) as a 0-dim float64 CUDA tensor."""
+    _shape_checks(gv.shape, kdims, F)
+    if gnorm2.numel() != 1:
+        raise ValueError("gnorm2 must hold one value")
     lib = load()
     _dev(gv, torch.complex64, "g")
     _dev(F, torch.complex64, "F")
@@ -161,7 +194,10 @@ def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None):
 
 
 def update(x, gv, eta, kdims=(1, 1, 1)):
-    """In place: x <- x - eta g."""
+    """In place: x <- x - eta g (x unchanged when eta is 0 or not finite)."""
+    _shape_checks(x.shape, like=gv)
+    if eta.numel() != 1:
+        raise ValueError("eta must hold one value")
     lib = load()
     _dev(x, torch.complex64, "x")
     _dev(gv, torch.complex64, "g")
@@ -172,9 +208,13 @@ def update(x, gv, eta, kdims=(1, 1, 1)):
 
 
 def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_steps=0, warm_start=True,
-          start_outer=0, out=None):
+          start_outer=0, out=None, ws=None, raise_nonfinite=True):
     """Algorithm 1 on the device.  ``schedule``: list of (lo, hi, steps).
-    Returns (x, trace) with trace a list of dicts (one per gradient step)."""
+    Returns (x, trace) with trace a list of dicts (one per gradient step).
+    ``ws``: optional uint8 CUDA workspace of at least solve_workspace_bytes()
+    bytes (allocated here otherwise).  With raise_nonfinite=False a run that
+    stops on a non-finite value returns (x, trace, status) instead of raising."""
+    _shape_checks(x0.shape, mask=mask, like=out, like_name="out")
     lib = load()
     _dev(x0, torch.complex64, "x0")
     if mask is not None:
@@ -198,11 +238,34 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     total = sum(int(s[2]) for s in schedule[start_outer:])
     tr = (Trace * max(1, total))()
     x = torch.empty_like(x0) if out is None else out
-    check(lib.hicu_solve(ctypes.byref(g), _ptr(x0), _ptr(mask), ctypes.byref(prm), _ptr(x), tr, _stream()),
-          "hicu_solve")
+    wsb = int(lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm)))
+    if wsb == 0:
+        raise ValueError("invalid solve arguments (geometry, rank, schedule or precision)")
+    if ws is None or ws.numel() < wsb:
+        ws = _workspace(wsb, x0.device)
+    st = lib.hicu_solve(ctypes.byref(g), _ptr(x0), _ptr(mask), ctypes.byref(prm), _ptr(x), tr, _ptr(ws), ws.numel(),
+                        _stream())
     trace = [dict(outer=t.outer, inner=t.inner, prec=t.prec, sweeps=t.sweeps, J=t.J, gnorm2=t.gnorm2, eta=t.eta)
              for t in tr[:total]]
+    if st == -4 and not raise_nonfinite:
+        return x, trace, st
+    check(st, "hicu_solve")
     return x, trace
+
+
+def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0):
+    """Device bytes hicu_solve needs for this problem and schedule."""
+    g = geom(shape, kdims)
+    n_outer = len(schedule)
+    steps = (ctypes.c_int32 * max(1, n_outer))(*[int(s[2]) for s in schedule])
+    regs = (ctypes.c_int64 * max(1, 6 * n_outer))(
+        *[int(v) for (lo, hi, _) in schedule for v in list(lo) + list(hi)])
+    prm = Params()
+    prm.rank, prm.p, prm.n_outer, prm.start_outer = int(rank), int(p), n_outer, int(start_outer)
+    prm.steps = ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32))
+    prm.regions = ctypes.cast(regs, ctypes.POINTER(ctypes.c_int64))
+    prm.prec, prm.refine_steps = _prec(prec), int(refine_steps)
+    return int(load().hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm)))
 
 
 def profile_begin():

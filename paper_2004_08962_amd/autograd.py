@@ -23,6 +23,7 @@ class HicuObjective(torch.autograd.Function):
     def forward(ctx, x, F, kdims, lo=None, hi=None, mask=None, prec="fp32"):
         if F.requires_grad:
             raise NotImplementedError("HicuObjective differentiates with respect to x only")
+        api._shape_checks(x.shape, kdims, F, mask)
         J, _, _ = api.objective_grad(x.detach(), None, F.detach(), kdims, lo, hi, prec=prec, want_grad=False)
         ctx.save_for_backward(x.detach(), F.detach())
         ctx.args = (tuple(kdims), lo, hi, mask, prec)

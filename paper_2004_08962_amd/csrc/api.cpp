@@ -95,7 +95,7 @@ int32_t hicu_gram(const hicu_geom* gm, const void* x, void* G, void* ws, size_t 
   Geo g;
   HICU_TRY(make_geo(gm, &g));
   if (!x || !G) return HICU_ERR_ARG;
-  ProfScope ps("gram", (hipStream_t)stream, 8.0 * (double)g.s * g.n * g.n, 8.0 * region_points(g) * g.nc);
+  ProfScope ps("gram", (hipStream_t)stream, 4.0 * (double)g.s * g.n * g.n, 8.0 * region_points(g) * g.nc);
   return launch_gram(g, x, G, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -170,22 +170,34 @@ int32_t hicu_update(const hicu_geom* gm, void* x, const void* gv, const double* 
                        g.npts * g.nc, (hipStream_t)stream);
 }
 
-int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, const hicu_params* prm, void* xout,
-                   hicu_trace* trace, void* stream) {
+}  // extern "C"
+
+namespace hicu {
+namespace {
+
+// Validated per-iteration geometries and the workspace layout of hicu_solve.
+struct SolvePlan {
+  std::vector<Geo> geos;
+  int64_t total_steps = 0;
+  int n = 0, nq = 0, pf = 0;
+  size_t ws_step = 0, ws_gram = 0;
+  size_t o_g, o_G, o_V0, o_V1, o_Q, o_F, o_sc, o_cnt, o_eig, o_gram, o_step, total;
+};
+
+int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* sp) {
   Geo full;
   HICU_TRY(make_geo(gm, &full));
-  if (!x0 || !xout || !prm || !prm->steps) return HICU_ERR_ARG;
+  if (!prm || !prm->steps) return HICU_ERR_ARG;
   if (!valid_prec(prm->prec) || prm->n_outer < 0 || prm->start_outer < 0 || prm->refine_steps < 0)
     return HICU_ERR_ARG;
   const int n = full.n, r = prm->rank;
   if (r < 0 || r >= n) return HICU_ERR_RANK;
-  const int nq = n - r;
   if (prm->p < 0) return HICU_ERR_RANK;
-  const int pf = prm->p == 0 ? nq : prm->p;
-  hipStream_t st = (hipStream_t)stream;
-  // Per-iteration geometries (validated up front: nothing runs on bad input).
-  std::vector<Geo> geos(prm->n_outer);
-  int64_t total_steps = 0;
+  sp->n = n;
+  sp->nq = n - r;
+  sp->pf = prm->p == 0 ? sp->nq : prm->p;
+  sp->geos.assign(prm->n_outer, Geo{});
+  sp->total_steps = 0;
   for (int i = 0; i < prm->n_outer; ++i) {
     hicu_geom gi = *gm;
     if (prm->regions) {
@@ -194,102 +206,143 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
         gi.hi[a] = prm->regions[i * 6 + 3 + a];
       }
     }
-    HICU_TRY(make_geo(&gi, &geos[i]));
+    HICU_TRY(make_geo(&gi, &sp->geos[i]));
     if (prm->steps[i] < 0) return HICU_ERR_ARG;
-    if (i >= prm->start_outer) total_steps += prm->steps[i];
+    if (i >= prm->start_outer) sp->total_steps += prm->steps[i];
   }
-  size_t ws_step = 0;
+  sp->ws_step = sp->ws_gram = 0;
   for (int i = prm->start_outer; i < prm->n_outer; ++i) {
-    ws_step = std::max(ws_step, step_workspace(geos[i], pf, prm->prec));
-    ws_step = std::max(ws_step, step_workspace(geos[i], pf, P_F32));
-    if (ws_step == 0) return HICU_ERR_UNSUPPORTED;
+    const size_t a = step_workspace(sp->geos[i], sp->pf, prm->prec), b = step_workspace(sp->geos[i], sp->pf, P_F32);
+    if (a == 0 || b == 0) return HICU_ERR_UNSUPPORTED;
+    sp->ws_step = std::max(sp->ws_step, std::max(a, b));
+    sp->ws_gram = std::max(sp->ws_gram, gram_workspace(sp->geos[i]));
   }
-  size_t ws_gram = 0;
-  for (int i = prm->start_outer; i < prm->n_outer; ++i) ws_gram = std::max(ws_gram, gram_workspace(geos[i]));
   const size_t N = (size_t)full.npts * full.nc;
   size_t off = 0;
-  const size_t o_g = off; off += al(N * sizeof(float2));
-  const size_t o_G = off; off += al((size_t)n * n * sizeof(double2));
-  const size_t o_V0 = off; off += al((size_t)n * n * sizeof(double2));
-  const size_t o_V1 = off; off += al((size_t)n * n * sizeof(double2));
-  const size_t o_Q = off; off += al((size_t)n * nq * sizeof(float2));
-  const size_t o_F = off; off += al((size_t)n * pf * sizeof(float2));
-  const size_t o_sc = off; off += al((size_t)std::max<int64_t>(1, total_steps) * 3 * sizeof(double));
-  const size_t o_eig = off; off += al(eig_workspace(n));
-  const size_t o_gram = off; off += al(ws_gram);
-  const size_t o_step = off; off += al(ws_step);
-  void* ws = nullptr;
-  HICU_HIP_TRY(hipMalloc(&ws, off));
-  struct Free {
-    void* p;
-    ~Free() { if (p) (void)hipFree(p); }
-  } guard{ws};
+  sp->o_g = off; off += al(N * sizeof(float2));
+  sp->o_G = off; off += al((size_t)n * n * sizeof(double2));
+  sp->o_V0 = off; off += al((size_t)n * n * sizeof(double2));
+  sp->o_V1 = off; off += al((size_t)n * n * sizeof(double2));
+  sp->o_Q = off; off += al((size_t)n * sp->nq * sizeof(float2));
+  sp->o_F = off; off += al((size_t)n * sp->pf * sizeof(float2));
+  sp->o_sc = off; off += al((size_t)std::max<int64_t>(1, sp->total_steps) * 3 * sizeof(double));
+  sp->o_cnt = off; off += al(sizeof(unsigned long long));
+  sp->o_eig = off; off += al(eig_workspace(n));
+  sp->o_gram = off; off += al(sp->ws_gram);
+  sp->o_step = off; off += al(sp->ws_step);
+  sp->total = off;
+  return HICU_OK;
+}
+
+}  // namespace
+}  // namespace hicu
+
+extern "C" {
+
+size_t hicu_solve_workspace_bytes(const hicu_geom* gm, const hicu_params* prm) {
+  SolvePlan sp;
+  return make_solve_plan(gm, prm, &sp) == HICU_OK ? sp.total : 0;
+}
+
+int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, const hicu_params* prm, void* xout,
+                   hicu_trace* trace, void* ws, size_t ws_bytes, void* stream) {
+  SolvePlan pl;
+  HICU_TRY(make_solve_plan(gm, prm, &pl));
+  if (!x0 || !xout) return HICU_ERR_ARG;
+  if (!ws || ws_bytes < pl.total) return HICU_ERR_WORKSPACE;
+  Geo full;
+  HICU_TRY(make_geo(gm, &full));
+  const int n = pl.n, r = prm->rank, nq = pl.nq, pf = pl.pf;
+  const int64_t total_steps = pl.total_steps;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)full.npts * full.nc;
   float2* x = reinterpret_cast<float2*>(xout);
-  float2* g = reinterpret_cast<float2*>(at(ws, o_g));
-  double* sc = reinterpret_cast<double*>(at(ws, o_sc));
+  float2* g = reinterpret_cast<float2*>(at(ws, pl.o_g));
+  double* sc = reinterpret_cast<double*>(at(ws, pl.o_sc));
+  // A non-finite input is rejected before anything is written.
+  {
+    unsigned long long bad = 0;
+    auto* cnt = reinterpret_cast<unsigned long long*>(at(ws, pl.o_cnt));
+    HICU_TRY(launch_count_nonfinite(reinterpret_cast<const float*>(x0), 2 * (int64_t)N, cnt, st));
+    HICU_HIP_TRY(hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HICU_HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return HICU_ERR_NONFINITE;
+  }
   if (xout != x0) HICU_HIP_TRY(hipMemcpyAsync(xout, x0, N * sizeof(float2), hipMemcpyDeviceToDevice, st));
-  std::vector<int32_t> sweeps_of(prm->n_outer, 0);
-  void* Vprev = at(ws, o_V0);
-  void* Vcur = at(ws, o_V1);
+  void* Vprev = at(ws, pl.o_V0);
+  void* Vcur = at(ws, pl.o_V1);
   bool have_prev = false;
   int32_t status = HICU_OK;
   int64_t step = 0;
-  std::vector<int32_t> prec_of(std::max<int64_t>(1, total_steps));
-  std::vector<int32_t> outer_of(prec_of.size()), inner_of(prec_of.size());
-  for (int i = prm->start_outer; i < prm->n_outer; ++i) {
-    const Geo& gi = geos[i];
+  std::vector<double> hs(3 * (size_t)std::max<int64_t>(1, total_steps));
+  for (int i = prm->start_outer; i < prm->n_outer && status != HICU_ERR_NONFINITE; ++i) {
+    const Geo& gi = pl.geos[i];
     {
-      ProfScope ps("gram", st, 8.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);
-      HICU_TRY(launch_gram(gi, x, at(ws, o_G), at(ws, o_gram), ws_gram, st));
+      ProfScope ps("gram", st, 4.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);
+      HICU_TRY(launch_gram(gi, x, at(ws, pl.o_G), at(ws, pl.o_gram), pl.ws_gram, st));
     }
     int32_t sw = 0;
     int32_t es;
     {
       ProfScope ps("eig", st);
-      es = run_eig(n, r, at(ws, o_G), (prm->warm_start && have_prev) ? Vprev : nullptr, at(ws, o_Q), nullptr, Vcur,
-                   &sw, at(ws, o_eig), eig_workspace(n), st,
-                   prm->p == 0);
+      es = run_eig(n, r, at(ws, pl.o_G), (prm->warm_start && have_prev) ? Vprev : nullptr, at(ws, pl.o_Q), nullptr,
+                   Vcur, &sw, at(ws, pl.o_eig), eig_workspace(n), st, prm->p == 0);
     }
     if (es < 0 && es != HICU_ERR_NOCONV) return es;
     if (es == HICU_ERR_NOCONV) status = HICU_ERR_NOCONV;
-    sweeps_of[i] = sw;
     std::swap(Vprev, Vcur);
     have_prev = true;
+    const int64_t step0 = step;
+    int prepped_prec = -1;  // precision whose weights of this iteration's F are in the workspace
     for (int j = 0; j < prm->steps[i]; ++j, ++step) {
       const int prec = (step >= total_steps - prm->refine_steps) ? P_F32 : prm->prec;
-      prec_of[step] = prec;
-      outer_of[step] = i;
-      inner_of[step] = j;
-      const void* F = at(ws, o_Q);
+      if (trace) {
+        trace[step].outer = i;
+        trace[step].inner = j;
+        trace[step].prec = prec;
+        trace[step].sweeps = sw;
+      }
+      const void* F = at(ws, pl.o_Q);
       if (prm->p > 0) {
         ProfScope ps("jl", st);
-        HICU_TRY(launch_jl(reinterpret_cast<const float2*>(at(ws, o_Q)), n, nq, pf, prm->seed, (uint32_t)i,
-                           (uint32_t)j, 0u, reinterpret_cast<float2*>(at(ws, o_F)), nullptr, st));
-        F = at(ws, o_F);
+        HICU_TRY(launch_jl(reinterpret_cast<const float2*>(at(ws, pl.o_Q)), n, nq, pf, prm->seed, (uint32_t)i,
+                           (uint32_t)j, 0u, reinterpret_cast<float2*>(at(ws, pl.o_F)), nullptr, st));
+        F = at(ws, pl.o_F);
+        prepped_prec = -1;  // a new F every step
       }
+      // Without JL the filters are fixed for the whole outer iteration, so
+      // their weight layouts are built once (again when the precision switches).
+      const int prep = prec == prepped_prec ? 0 : kPrepAll;
+      prepped_prec = prec;
       double* Jd = sc + 3 * step;
-      HICU_TRY(objective_grad_impl(gi, x, mask, F, pf, prec, Jd, g, Jd + 1, at(ws, o_step), ws_step, st));
-      HICU_TRY(line_search_impl(gi, g, Jd + 1, F, pf, prec, Jd + 2, at(ws, o_step), ws_step, st));
+      HICU_TRY(objective_grad_impl(gi, x, mask, F, pf, prec, Jd, g, Jd + 1, at(ws, pl.o_step), pl.ws_step, st, prep));
+      HICU_TRY(line_search_impl(gi, g, Jd + 1, F, pf, prec, Jd + 2, at(ws, pl.o_step), pl.ws_step, st, true));
       ProfScope ps("update", st, 0.0, 24.0 * (double)N);
       HICU_TRY(launch_update(x, g, Jd + 2, (int64_t)N, st));
     }
-  }
-  std::vector<double> hs((size_t)std::max<int64_t>(1, total_steps) * 3);
-  if (total_steps > 0)
-    HICU_HIP_TRY(hipMemcpyAsync(hs.data(), sc, (size_t)total_steps * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HICU_HIP_TRY(hipStreamSynchronize(st));
-  for (int64_t s = 0; s < total_steps; ++s) {
-    if (!std::isfinite(hs[3 * s]) || !std::isfinite(hs[3 * s + 1])) status = HICU_ERR_NONFINITE;
-    if (trace) {
-      trace[s].outer = outer_of[s];
-      trace[s].inner = inner_of[s];
-      trace[s].prec = prec_of[s];
-      trace[s].sweeps = sweeps_of[outer_of[s]];
-      trace[s].J = hs[3 * s];
-      trace[s].gnorm2 = hs[3 * s + 1];
-      trace[s].eta = hs[3 * s + 2];
+    // The step scalars of this iteration: a non-finite J or gradient stops the
+    // run.  The line search turns any non-finite scalar into a zero step and
+    // the update skips zero steps, so x stays at its last finite iterate.
+    const int64_t cnt = step - step0;
+    if (cnt > 0) {
+      HICU_HIP_TRY(hipMemcpyAsync(hs.data() + 3 * step0, sc + 3 * step0, (size_t)cnt * 3 * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+      HICU_HIP_TRY(hipStreamSynchronize(st));
+    }
+    for (int64_t s = step0; s < step; ++s) {
+      if (!std::isfinite(hs[3 * s]) || !std::isfinite(hs[3 * s + 1]) || !std::isfinite(hs[3 * s + 2]))
+        status = HICU_ERR_NONFINITE;
+      if (trace) {
+        trace[s].J = hs[3 * s];
+        trace[s].gnorm2 = hs[3 * s + 1];
+        trace[s].eta = hs[3 * s + 2];
+      }
     }
   }
+  // Steps not run after a stop keep zero scalars in the trace.
+  if (trace)
+    for (int64_t s = step; s < total_steps; ++s) trace[s] = hicu_trace{-1, -1, -1, 0, 0.0, 0.0, 0.0};
+  HICU_HIP_TRY(hipStreamSynchronize(st));
   return status;
 }
 

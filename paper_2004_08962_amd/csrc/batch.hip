@@ -114,6 +114,7 @@ __global__ __launch_bounds__(1024) void eta_batch_kernel(const RedItem* items) {
 __global__ void update_batch_kernel(const UpdItem* items) {
   const UpdItem it = items[blockIdx.y];
   const double e = *it.eta;
+  if (!(e != 0.0) || !isfinite(e)) return;  // zero or non-finite step: x untouched
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < it.count;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float2 gv = it.g[i];

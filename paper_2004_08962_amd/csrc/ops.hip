@@ -99,9 +99,12 @@ int32_t launch_eta(const double* part, int64_t count, const double* gnorm2, doub
   return HICU_OK;
 }
 
-// x <- x - eta g, evaluated in FP64 and rounded once.
+// x <- x - eta g, evaluated in FP64 and rounded once.  A zero or non-finite
+// eta leaves x untouched (the line search returns 0 for a zero gradient and
+// for any non-finite scalar, so a poisoned gradient never reaches x).
 __global__ void update_kernel(float2* x, const float2* g, const double* eta, int64_t count) {
   const double e = *eta;
+  if (!(e != 0.0) || !isfinite(e)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
     const float2 gv = g[i];
     float2 xv = x[i];
@@ -114,6 +117,32 @@ __global__ void update_kernel(float2* x, const float2* g, const double* eta, int
 int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t count, hipStream_t st) {
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256), 16384));
   hipLaunchKernelGGL(update_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, g, eta, count);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+// Number of non-finite floats among v[0..count) added into *out (grid-stride,
+// one atomic per block).
+__global__ __launch_bounds__(256) void nonfinite_kernel(const float* v, int64_t count, unsigned long long* out) {
+  __shared__ unsigned int red[4];
+  unsigned int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    c += isfinite(v[i]) ? 0u : 1u;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int t = red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(out, (unsigned long long)t);
+  }
+}
+
+__global__ void clear_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+int32_t launch_count_nonfinite(const float* v, int64_t count, unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(clear_u64_kernel, dim3(1), dim3(1), 0, st, out);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(count, 256), 4096));
+  hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, v, count, out);
   HICU_HIP_TRY(hipGetLastError());
   return HICU_OK;
 }

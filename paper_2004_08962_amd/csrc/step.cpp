@@ -207,13 +207,14 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
 // over groups is the full adjoint because H_S'(Y F^H) is linear in the
 // filter columns; the last group writes the per-block sums of |g|^2.
 int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
-                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st) {
+                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st,
+                            int prep) {
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, gout != nullptr, &sp));
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
   const float2* Fc = reinterpret_cast<const float2*>(F);
   const double nS = (double)region_points(g);
-  {
+  if (prep & kPrepForward) {
     ProfScope ps("prep_weights", st);
     HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, at(ws, sp.off_Bf), at(ws, sp.off_Bflo), st));
   }
@@ -235,8 +236,10 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
       ProfScope ps("zero", st);
       HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
     }
-    ProfScope ps("prep_weights", st);
-    HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
+    if (prep & kPrepAdjoint) {
+      ProfScope ps("prep_weights", st);
+      HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
+    }
   }
   int64_t pf_used = 0;
   const double ybytes = sp.ybw ? 4.0 : 8.0;  // bytes per stored residual value
@@ -310,13 +313,26 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
 }
 
 int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
-                         double* eta, void* ws, size_t ws_bytes, hipStream_t st) {
+                         double* eta, void* ws, size_t ws_bytes, hipStream_t st, bool grad_weights) {
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, false, &sp));
   // The line-search layout is a prefix-compatible subset of the gradient
-  // layout only when no Y is stored, so use its own offsets.
+  // layout only when no Y is stored, so it has its own offsets.  With
+  // grad_weights the forward weights that objective_grad_impl prepared for
+  // the same F, precision and geometry are read where the gradient layout
+  // put them (the forward plan is the same in both layouts).
+  if (grad_weights) {
+    StepPlan gp;
+    HICU_TRY(make_step_plan(g, p, prec, true, &gp));
+    if (!ws || ws_bytes < gp.total) return HICU_ERR_WORKSPACE;
+    sp.off_Bf = gp.off_Bf;
+    sp.off_Bflo = gp.off_Bflo;
+    sp.off_pz = gp.off_pz;
+    sp.off_sc = gp.off_sc;
+    sp.off_pmax = gp.off_pmax;
+  }
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
-  {
+  if (!grad_weights) {
     ProfScope ps("prep_weights", st);
     HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
                                  at(ws, sp.off_Bflo), st));

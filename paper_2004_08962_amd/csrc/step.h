@@ -52,10 +52,18 @@ void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, flo
 void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const void* Blo, void* gout,
                        const uint8_t* mask, double* partial, ConvArgs& a);
 
+// Which filter-weight layouts objective_grad_impl builds from F before its
+// contractions.  A caller that ran it on the same F, precision, geometry and
+// workspace earlier may skip the rebuild (the weights are left in place).
+constexpr int kPrepForward = 1, kPrepAdjoint = 2, kPrepAll = 3;
+
 int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
-                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st);
+                            double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st,
+                            int prep = kPrepAll);
+// grad_weights: reuse the forward weights objective_grad_impl left in the
+// same workspace for the same F, precision and geometry (no rebuild).
 int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
-                         double* eta, void* ws, size_t ws_bytes, hipStream_t st);
+                         double* eta, void* ws, size_t ws_bytes, hipStream_t st, bool grad_weights = false);
 size_t step_workspace(const Geo& g, int p, int prec);
 
 }  // namespace hicu

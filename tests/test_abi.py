@@ -97,3 +97,33 @@ def test_workspace_sizes(lib):
     assert lib.hicu_gram_workspace_bytes(ctypes.byref(g)) > 0
     assert lib.hicu_nullspace_workspace_bytes(400) >= 3 * 416 * 416 * 16
     assert lib.hicu_workspace_bytes(ctypes.byref(g), 280, 9) == 0
+
+
+def _params(rank=30, steps=(5, 5), p=0, prec=0):
+    from paper_2004_08962_amd._lib import Params
+    prm = Params()
+    st = (ctypes.c_int32 * len(steps))(*steps)
+    prm.rank, prm.p, prm.n_outer, prm.start_outer = rank, p, len(steps), 0
+    prm.steps = ctypes.cast(st, ctypes.POINTER(ctypes.c_int32))
+    prm.regions = None
+    prm.seed, prm.prec, prm.refine_steps, prm.warm_start = 0, prec, 0, 1
+    return prm, st
+
+
+def test_solve_workspace_is_the_callers(lib):
+    """hicu_solve allocates nothing: it sizes its workspace up front and
+    refuses a missing or short one before any launch."""
+    g = _geom()
+    prm, keep = _params()
+    b = lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm))
+    n = 100
+    assert b >= 3 * n * n * 16 + 64 * 64 * 4 * 8  # G, two eigenvector sets, the gradient
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.hicu_solve(ctypes.byref(g), fake, None, ctypes.byref(prm), fake, None, None, 0, None) == -6
+    assert lib.hicu_solve(ctypes.byref(g), fake, None, ctypes.byref(prm), fake, None, fake, b - 1, None) == -6
+    assert lib.hicu_solve(ctypes.byref(g), None, None, ctypes.byref(prm), fake, None, fake, b, None) == -1
+    bad, keep2 = _params(rank=100)
+    assert lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
+    assert lib.hicu_solve(ctypes.byref(g), fake, None, ctypes.byref(bad), fake, None, fake, b, None) == -3
+    badp, keep3 = _params(prec=9)
+    assert lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(badp)) == 0
