@@ -108,6 +108,20 @@ size_t hicu_gram_workspace_bytes(const hicu_geom* geom);
 int32_t hicu_gram(const hicu_geom* geom, const void* x_dev, void* G_dev,
                   void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Route of hicu_gram (process-wide; default 1).  Both give G to FP64
+ * rounding from the same exact products:
+ *   1  shift correlation: G[(k,c),(k+d,c')] depends on the tap pair only
+ *      through the shift d and the window of summation points, so the
+ *      region is cut into cells (single planes near both ends of each axis
+ *      and one core segment) whose coil-by-coil correlation sums for every
+ *      shift d >= 0 are formed once on the FP64 matrix cores and added per
+ *      window: (2K-1)^D/2 shifts x Nc^2 coil pairs x |S| points of work
+ *      instead of n^2 s / 2.  Up to 32 coils (more use route 0).
+ *   0  direct products over the upper block triangle of the real Gram.
+ * The workspace size covers both routes.  Returns HICU_OK, or
+ * HICU_ERR_ARG for another value. */
+int32_t hicu_set_gram_route(int32_t route);
+
 /* ------------------------------------------------------------------------
  * Nullspace basis from the Gram (THEORY: J(x) of Eq. 1 equals
  * min ||H(x) Q||_F^2 over orthonormal Q with n - r columns; Algorithm 1,

@@ -30,11 +30,11 @@ from .nullspace import gram, nullspace
 from .jl import philox4x32_10, philox_normals, jl_matrix
 from .descent import objective_grad, line_search, descent_step, solve, objective
 from .metrics import ser, rel_err
-from .pointwise import grad_at_points, residual_at_points
+from .pointwise import grad_at_points, residual_at_points, gram_entries
 
 __all__ = [
     "valid_extent", "hankel_matrix", "hankel_adjoint", "forward", "adjoint", "gram",
     "nullspace", "philox4x32_10", "philox_normals", "jl_matrix", "objective_grad",
     "line_search", "descent_step", "solve", "objective", "ser", "rel_err",
-    "grad_at_points", "residual_at_points",
+    "grad_at_points", "residual_at_points", "gram_entries",
 ]

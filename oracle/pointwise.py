@@ -6,6 +6,10 @@ row Y[u, :] = patch(u) . F with patch(u)[(k, c)] = x[u + k, c], and the
 gradient entry g[w, c] = 2 sum over taps k with u = w - k a valid output of
 sum_j Y[u, j] conj(F[(k, c), j]), zero at observed locations.
 
+Gram entries G[(k, c), (k', c')] = sum over valid outputs u of
+conj(x[u + k, c]) x[u + k', c'] (the Gram of H on the region, DISCUSSION
+section) one at a time, as the inner product of two shifted windows.
+
 Parity: checked against the explicit-matrix functions on small inputs.
 """
 import numpy as np
@@ -45,4 +49,31 @@ def grad_at_points(x, mask, F, kdims, lo, hi, points):
                         acc += Fc[t * nc:(t + 1) * nc, :] @ y
                     t += 1
         out[idx] = 2.0 * acc
+    return out
+
+
+def gram_entries(x, kdims, lo, hi, pairs):
+    """Entries G[i, j] of the Gram H'H for flat tap indices i = (k, c),
+    j = (k', c') (kernel offset lexicographic, coil fastest), each the inner
+    product of the windows of x shifted by k and k'.  Returns complex128."""
+    x = np.asarray(x, np.complex128)
+    nc = x.shape[3]
+    m = [hi[a] - lo[a] - kdims[a] + 1 for a in range(3)]
+
+    def split(i):
+        t, c = divmod(int(i), nc)
+        k2 = t % kdims[2]
+        k1 = (t // kdims[2]) % kdims[1]
+        k0 = t // (kdims[2] * kdims[1])
+        return (k0, k1, k2), c
+
+    def window(k, c):
+        return x[lo[0] + k[0]:lo[0] + k[0] + m[0], lo[1] + k[1]:lo[1] + k[1] + m[1],
+                 lo[2] + k[2]:lo[2] + k[2] + m[2], c].reshape(-1)
+
+    out = np.zeros(len(pairs), np.complex128)
+    for idx, (i, j) in enumerate(pairs):
+        k, c = split(i)
+        kp, cp = split(j)
+        out[idx] = np.vdot(window(k, c), window(kp, cp))
     return out

@@ -62,6 +62,7 @@ SIGNATURES = {
     "hicu_num_outputs": (c_int64, [ctypes.POINTER(Geom)]),
     "hicu_gram_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom)]),
     "hicu_gram": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "hicu_set_gram_route": (c_int32, [c_int32]),
     "hicu_nullspace_workspace_bytes": (c_size_t, [c_int32]),
     "hicu_nullspace": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  ctypes.POINTER(c_int32), c_void_p, c_size_t, c_void_p]),

@@ -95,6 +95,11 @@ def gram(x, kdims, lo=None, hi=None):
     return G
 
 
+def set_gram_route(route):
+    """1: shift-correlation Gram (default), 0: direct products (both FP64)."""
+    check(load().hicu_set_gram_route(int(route)), "hicu_set_gram_route")
+
+
 def nullspace(G, rank, V0=None, want_V=True):
     """Returns (Q complex64 (n, n-r), evals float64 (n,), V complex128 or None, sweeps)."""
     if G.dim() != 2 or G.shape[0] != G.shape[1]:

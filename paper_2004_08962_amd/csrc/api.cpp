@@ -99,6 +99,12 @@ int32_t hicu_gram(const hicu_geom* gm, const void* x, void* G, void* ws, size_t 
   return launch_gram(g, x, G, ws, ws_bytes, (hipStream_t)stream);
 }
 
+int32_t hicu_set_gram_route(int32_t route) {
+  if (route != 0 && route != 1) return HICU_ERR_ARG;
+  set_gram_route(route);
+  return HICU_OK;
+}
+
 size_t hicu_nullspace_workspace_bytes(int32_t n) { return n < 1 ? 0 : eig_workspace(n); }
 
 int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G, const void* V0, void* Q, double* evals, void* V,

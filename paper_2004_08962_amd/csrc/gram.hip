@@ -10,9 +10,27 @@
 // read 16 consecutive floats), widened to FP64 and accumulated by
 // v_mfma_f64_16x16x4.  Per-range partial tiles are summed in a fixed order
 // by a second kernel, so the result is deterministic.
+//
+// Shift-correlation route (the default for up to 32 coils).  The entry for
+// taps k and k' = k + d only depends on the shift d and on the window
+// W_k = {u + k : u valid} of summation points:
+//   G[(k,c),(k+d,c')] = sum_{w in W_k} conj(x[w,c]) x[w+d,c'].
+// Along each axis the K windows [lo+k, lo+k+m) share their interior, so the
+// region splits into segments (single planes near both ends and one core
+// segment), every window is a union of K consecutive segments, and the
+// region into cells (products of segments).  One pass over the region
+// computes, for every cell and every shift d >= 0 (lexicographic order; the
+// rest of G follows by Hermitian symmetry), the coil-by-coil correlation sum
+// of the cell on the FP64 matrix cores; G is then assembled from the cell
+// sums of each window in a fixed order.  Every product is formed exactly as
+// in the direct route (FP32 values widened to FP64), only the grouping of
+// the sums differs, and the work falls from n^2 s / 2 complex products to
+// (2K-1)^D / 2 shifts x Nc^2 coil pairs x |S| points.
 #include <algorithm>
+#include <atomic>
 
 #include "gram.h"
+#include "step.h"
 
 namespace hicu {
 
@@ -198,14 +216,327 @@ static void gram_layout(const Geo& g, int* ntile, int* ntri, int* ngroups, int64
   *ngroups = (int)cdiv(g.s, *qper);
 }
 
-size_t gram_workspace(const Geo& g) {
-  int ntile, ntri, ngroups;
-  int64_t qper;
-  gram_layout(g, &ntile, &ntri, &ngroups, &qper);
-  return (size_t)ngroups * ntri * 4096 * sizeof(double);
+
+
+// ---------------------------------------------------------------------------
+// Shift-correlation route
+// ---------------------------------------------------------------------------
+
+// Route of launch_gram: 1 = shift correlation (when the coil count allows),
+// 0 = direct products over the upper block triangle.  Process-wide.
+static std::atomic<int> g_route{1};
+int gram_route() { return g_route.load(); }
+void set_gram_route(int r) { g_route.store(r == 0 ? 0 : 1); }
+
+// Segments of one axis of the region [lo, lo + m + K - 1): with m >= K, K - 1
+// single planes, the core [lo + K - 1, lo + m) and K - 1 single planes, and
+// window k is segments [k, k + K); with m < K every plane is a segment and
+// window k is segments [k, k + m).
+struct AxisSegs {
+  int64_t lo, m;
+  int K;
+  __host__ __device__ int count() const { return m >= K ? 2 * K - 1 : (int)(m + K - 1); }
+  __host__ __device__ int64_t start(int j) const {
+    if (m < K) return lo + j;
+    return j < K ? lo + j : lo + m + (j - K);
+  }
+  __host__ __device__ int64_t len(int j) const { return (m >= K && j == K - 1) ? m - K + 1 : 1; }
+  // segments of window k: [k, k + width())
+  __host__ __device__ int width() const { return m >= K ? K : (int)m; }
+};
+
+struct CorrArgs {
+  const float* x;
+  int64_t d1, d2;          // array extents of axes 1, 2
+  int nc;
+  int64_t lo[3], hi[3];    // region
+  int K[3];
+  AxisSegs ax[3];
+  int ncell;
+  int nd_half;             // shifts d >= 0 (lexicographic)
+  int64_t chunk;           // points per work entry
+  int nent;                // work entries
+  int ne, W;               // W = 16 T real components per tile side, ne = W^2
+  int* ent_cell;           // [nent] cell of each entry
+  int64_t* ent_q;          // [nent][2] point range of each entry inside its cell box
+  int* cell_ent;           // [ncell][2] first entry and entry count
+  double* part;            // [nent][nd_half][ne]  real-embedding partial sums
+  double* cellsum;         // [ncell][nd_half][ne] (cells with several entries)
+};
+
+__host__ __device__ inline void cell_box(const CorrArgs& a, int cell, int64_t* st, int64_t* ln) {
+  const int n2 = a.ax[2].count(), n1 = a.ax[1].count();
+  const int j2 = cell % n2, j1 = (cell / n2) % n1, j0 = cell / (n2 * n1);
+  st[0] = a.ax[0].start(j0);
+  st[1] = a.ax[1].start(j1);
+  st[2] = a.ax[2].start(j2);
+  ln[0] = a.ax[0].len(j0);
+  ln[1] = a.ax[1].len(j1);
+  ln[2] = a.ax[2].len(j2);
 }
 
+// Work entries: each cell's points (row-major inside the cell box) in chunks
+// of a.chunk; one thread walks the cells in order (a few thousand at most).
+__global__ void corr_plan_kernel(CorrArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int e = 0;
+  for (int c = 0; c < a.ncell; ++c) {
+    int64_t st[3], ln[3];
+    cell_box(a, c, st, ln);
+    const int64_t np = ln[0] * ln[1] * ln[2];
+    const int cnt = (int)((np + a.chunk - 1) / a.chunk);
+    a.cell_ent[2 * c] = e;
+    a.cell_ent[2 * c + 1] = cnt;
+    for (int i = 0; i < cnt; ++i, ++e) {
+      a.ent_cell[e] = c;
+      a.ent_q[2 * e] = (int64_t)i * a.chunk;
+      a.ent_q[2 * e + 1] = min(np, (int64_t)(i + 1) * a.chunk);
+    }
+  }
+}
+
+// Shift number h (0 = zero shift) -> d, in lexicographic order of d >= 0.
+__host__ __device__ inline void shift_of(const CorrArgs& a, int h, int* d) {
+  const int w2 = 2 * a.K[2] - 1, w1 = 2 * a.K[1] - 1, w0 = 2 * a.K[0] - 1;
+  const int dl = h + (w0 * w1 * w2 - 1) / 2;
+  d[2] = dl % w2 - (a.K[2] - 1);
+  d[1] = (dl / w2) % w1 - (a.K[1] - 1);
+  d[0] = dl / (w2 * w1) - (a.K[0] - 1);
+}
+
+// Workgroup = (entry, group of 4 shifts); wave v takes shift 4 * group + v
+// and accumulates the T x T grid of 16 x 16 real-embedding tiles of
+// sum_w x[w] x[w + d]^T with v_mfma_f64_16x16x4 (4 points per step; lane
+// group g takes points g, g + 4, ...).  x[w + d] outside the region counts as
+// zero (such cell/shift pairs are never assembled).  Operands are fetched
+// kGramAhead steps ahead and widened to FP64 at use.
+template <int T>
+__global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
+  const int ngrp = (a.nd_half + 3) / 4;
+  const int64_t lin = gram_remap(blockIdx.x, (int64_t)a.nent * ngrp);
+  const int ent = (int)(lin / ngrp), grp = (int)(lin % ngrp);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
+  const int h = grp * 4 + wave;
+  if (h >= a.nd_half) return;
+  int d[3];
+  shift_of(a, h, d);
+  int64_t cst[3], cln[3];
+  cell_box(a, a.ent_cell[ent], cst, cln);
+  const int64_t q_begin = a.ent_q[2 * ent], q_end = a.ent_q[2 * ent + 1];
+  const int two_nc = 2 * a.nc;
+  bool okc[T];
+#pragma unroll
+  for (int i = 0; i < T; ++i) okc[i] = 16 * i + m < two_nc;
+  const int64_t dOff = ((int64_t)d[0] * a.d1 * a.d2 + (int64_t)d[1] * a.d2 + d[2]) * two_nc;
+
+  double4_t acc[T][T];
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int j = 0; j < T; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  int64_t q = q_begin + g;
+  int64_t p2 = q % cln[2], p1 = (q / cln[2]) % cln[1], p0 = q / (cln[2] * cln[1]);
+  auto fetch = [&](float (&av)[T], float (&bv)[T]) {
+    const bool ok = q < q_end;
+    const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
+    const int64_t v0 = w0 + d[0], v1 = w1 + d[1], v2 = w2 + d[2];
+    const bool okb = ok && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] && v2 >= a.lo[2] &&
+                     v2 < a.hi[2];
+    const int64_t base = ok ? ((w0 * a.d1 + w1) * a.d2 + w2) * two_nc : 0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
+      bv[i] = (okb && okc[i]) ? a.x[base + dOff + 16 * i + m] : 0.f;
+    }
+    q += 4;
+    p2 += 4;
+    while (p2 >= cln[2]) {
+      p2 -= cln[2];
+      if (++p1 == cln[1]) {
+        p1 = 0;
+        ++p0;
+      }
+    }
+  };
+  constexpr int PF = kGramAhead;
+  float av[PF][T], bv[PF][T];
+#pragma unroll
+  for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+      if (q0 + 4 * r >= q_end) break;
+      double ad[T], bd[T];
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        ad[i] = (double)av[r][i];
+        bd[i] = (double)bv[r][i];
+      }
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[i][j], 0, 0, 0);
+      fetch(av[r], bv[r]);  // the step PF positions further on
+    }
+  }
+  // v_mfma_f64_16x16x4: lane holds rows g, g + 4, g + 8, g + 12 of column m
+  double* out = a.part + ((size_t)ent * a.nd_half + h) * a.ne;
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int j = 0; j < T; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(16 * i + g + 4 * r) * a.W + 16 * j + m] = acc[i][j][r];
+}
+
+// Cells split over several entries: their partial sums added in entry order.
+__global__ __launch_bounds__(256) void corr_reduce_kernel(CorrArgs a) {
+  const int cell = blockIdx.y;
+  const int first = a.cell_ent[2 * cell], cnt = a.cell_ent[2 * cell + 1];
+  if (cnt <= 1) return;
+  const int64_t per = (int64_t)a.nd_half * a.ne;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < cnt; ++i) s += a.part[(size_t)(first + i) * per + e];
+    a.cellsum[(size_t)cell * per + e] = s;
+  }
+}
+
+// G from the cell sums: one thread per (tap k, shift h, coil pair); the
+// window W_k is the product of each axis's segments [k_a, k_a + width),
+// summed in cell order; the mirrored entry is the conjugate, so G is exactly
+// Hermitian with a real diagonal.
+__global__ __launch_bounds__(256) void corr_assemble_kernel(CorrArgs a, int n, double2* G) {
+  const int nc = a.nc;
+  const int64_t total = (int64_t)a.K[0] * a.K[1] * a.K[2] * a.nd_half * nc * nc;
+  const int64_t per = (int64_t)a.nd_half * a.ne;
+  const int n2 = a.ax[2].count(), n1 = a.ax[1].count();
+  const int wd0 = a.ax[0].width(), wd1 = a.ax[1].width(), wd2 = a.ax[2].width();
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int cp = (int)(t % nc), c = (int)((t / nc) % nc);
+    const int h = (int)((t / ((int64_t)nc * nc)) % a.nd_half);
+    const int kl = (int)(t / ((int64_t)nc * nc * a.nd_half));
+    const int k2 = kl % a.K[2], k1 = (kl / a.K[2]) % a.K[1], k0 = kl / (a.K[2] * a.K[1]);
+    int d[3];
+    shift_of(a, h, d);
+    const int q0 = k0 + d[0], q1 = k1 + d[1], q2 = k2 + d[2];
+    if (q0 < 0 || q0 >= a.K[0] || q1 < 0 || q1 >= a.K[1] || q2 < 0 || q2 >= a.K[2]) continue;
+    if (h == 0 && cp < c) continue;  // zero shift: upper triangle of the coil block, mirrored below
+    double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
+    const int e_rr = (2 * c) * a.W + 2 * cp, e_ii = (2 * c + 1) * a.W + 2 * cp + 1;
+    const int e_ri = (2 * c) * a.W + 2 * cp + 1, e_ir = (2 * c + 1) * a.W + 2 * cp;
+    for (int j0 = k0; j0 < k0 + wd0; ++j0)
+      for (int j1 = k1; j1 < k1 + wd1; ++j1)
+        for (int j2 = k2; j2 < k2 + wd2; ++j2) {
+          const int cell = (j0 * n1 + j1) * n2 + j2;
+          const int first = a.cell_ent[2 * cell], cnt = a.cell_ent[2 * cell + 1];
+          const double* src =
+              (cnt > 1 ? a.cellsum + (size_t)cell * per : a.part + (size_t)first * per) + (size_t)h * a.ne;
+          rr += src[e_rr];
+          ii += src[e_ii];
+          ri += src[e_ri];
+          ir += src[e_ir];
+        }
+    const int i = kl * nc + c, jj = ((q0 * a.K[1] + q1) * a.K[2] + q2) * nc + cp;
+    const double re = rr + ii, im = i == jj ? 0.0 : ri - ir;
+    G[(size_t)i * n + jj] = make_double2(re, im);
+    if (i != jj) G[(size_t)jj * n + i] = make_double2(re, -im);
+  }
+}
+
+namespace {
+
+constexpr int kCorrMaxCoils = 32;  // T <= 4 tiles of 16 real components
+
+struct CorrPlan {
+  CorrArgs a;
+  int T;
+  size_t off_ent_cell, off_ent_q, off_cell_ent, off_part, off_cellsum, total;
+};
+
+bool corr_plan(const Geo& g, CorrPlan* p) {
+  if (g.nc > kCorrMaxCoils) return false;
+  CorrArgs& a = p->a;
+  a = CorrArgs{};
+  a.nc = g.nc;
+  a.d1 = g.d[1];
+  a.d2 = g.d[2];
+  for (int i = 0; i < 3; ++i) {
+    a.lo[i] = g.lo[i];
+    a.hi[i] = g.hi[i];
+    a.K[i] = g.k[i];
+    a.ax[i].lo = g.lo[i];
+    a.ax[i].m = g.m[i];
+    a.ax[i].K = g.k[i];
+  }
+  a.ncell = a.ax[0].count() * a.ax[1].count() * a.ax[2].count();
+  if (a.ncell > 65535) return false;  // the reduce launch puts cells on grid axis y
+  a.nd_half = ((2 * g.k[0] - 1) * (2 * g.k[1] - 1) * (2 * g.k[2] - 1) + 1) / 2;
+  p->T = (int)cdiv(2 * g.nc, 16);
+  a.W = 16 * p->T;
+  a.ne = a.W * a.W;
+  const int64_t npts = region_points(g);
+  a.chunk = std::max<int64_t>(2048, std::min<int64_t>(131072, rup(npts / 64, 4)));
+  int64_t nent = 0, multi = 0;
+  for (int c = 0; c < a.ncell; ++c) {
+    int64_t st[3], ln[3];
+    cell_box(a, c, st, ln);
+    const int64_t k = cdiv(ln[0] * ln[1] * ln[2], a.chunk);
+    nent += k;
+    multi += k > 1;
+  }
+  const int64_t ngrp = (a.nd_half + 3) / 4;
+  if (nent > (1 << 24) || nent * ngrp > 0x7fffffffLL) return false;
+  a.nent = (int)nent;
+  const size_t per = (size_t)a.nd_half * a.ne * sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) / 256 * 256;
+    return o;
+  };
+  p->off_ent_cell = take((size_t)nent * sizeof(int));
+  p->off_ent_q = take(2 * (size_t)nent * sizeof(int64_t));
+  p->off_cell_ent = take(2 * (size_t)a.ncell * sizeof(int));
+  p->off_part = take((size_t)nent * per);
+  p->off_cellsum = take(multi > 0 ? (size_t)a.ncell * per : 0);
+  p->total = off;
+  return true;
+}
+
+}  // namespace
+
 int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_bytes, hipStream_t st) {
+  CorrPlan cp;
+  if (gram_route() == 1 && corr_plan(g, &cp)) {
+    if (ws == nullptr || ws_bytes < cp.total) return HICU_ERR_WORKSPACE;
+    CorrArgs a = cp.a;
+    char* b = reinterpret_cast<char*>(ws);
+    a.x = reinterpret_cast<const float*>(x);
+    a.ent_cell = reinterpret_cast<int*>(b + cp.off_ent_cell);
+    a.ent_q = reinterpret_cast<int64_t*>(b + cp.off_ent_q);
+    a.cell_ent = reinterpret_cast<int*>(b + cp.off_cell_ent);
+    a.part = reinterpret_cast<double*>(b + cp.off_part);
+    a.cellsum = reinterpret_cast<double*>(b + cp.off_cellsum);
+    hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(64), 0, st, a);
+    const int ngrp = (a.nd_half + 3) / 4;
+    const dim3 grid((unsigned)((int64_t)a.nent * ngrp));
+    switch (cp.T) {
+      case 1: hipLaunchKernelGGL(corr_kernel<1>, grid, dim3(256), 0, st, a); break;
+      case 2: hipLaunchKernelGGL(corr_kernel<2>, grid, dim3(256), 0, st, a); break;
+      case 3: hipLaunchKernelGGL(corr_kernel<3>, grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL(corr_kernel<4>, grid, dim3(256), 0, st, a); break;
+    }
+    const int64_t per = (int64_t)a.nd_half * a.ne;
+    hipLaunchKernelGGL(corr_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(per, 256), 1024), a.ncell),
+                       dim3(256), 0, st, a);
+    const int64_t tot = (int64_t)g.k[0] * g.k[1] * g.k[2] * a.nd_half * g.nc * g.nc;
+    hipLaunchKernelGGL(corr_assemble_kernel, dim3((unsigned)std::min<int64_t>(cdiv(tot, 256), 65536)), dim3(256), 0,
+                       st, a, g.n, reinterpret_cast<double2*>(G));
+    HICU_HIP_TRY(hipGetLastError());
+    return HICU_OK;
+  }
   int ntile, ntri, ngroups;
   int64_t qper;
   gram_layout(g, &ntile, &ntri, &ngroups, &qper);
@@ -236,6 +567,15 @@ int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_by
                      ntri, ntile, g.n, reinterpret_cast<double2*>(G));
   HICU_HIP_TRY(hipGetLastError());
   return HICU_OK;
+}
+
+size_t gram_workspace(const Geo& g) {
+  int ntile, ntri, ngroups;
+  int64_t qper;
+  gram_layout(g, &ntile, &ntri, &ngroups, &qper);
+  const size_t direct = (size_t)ngroups * ntri * 4096 * sizeof(double);
+  CorrPlan cp;
+  return std::max(direct, corr_plan(g, &cp) ? cp.total : (size_t)0);
 }
 
 }  // namespace hicu

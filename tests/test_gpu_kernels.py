@@ -70,11 +70,16 @@ def _filters(x, kd, lo, hi, p, seed):
     return F.astype(np.complex64)
 
 
+@pytest.mark.parametrize("route", [1, 0], ids=["shift_corr", "direct"])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
-def test_gram(hc, case):
+def test_gram(hc, case, route):
     name, x, mask, kd, lo, hi = case
-    print("gram", name, x.shape, kd, lo, hi, flush=True)
-    G = _host(hc.gram(_dev(x), kd, lo, hi))
+    print("gram", name, x.shape, kd, lo, hi, "route", route, flush=True)
+    hc.set_gram_route(route)
+    try:
+        G = _host(hc.gram(_dev(x), kd, lo, hi))
+    finally:
+        hc.set_gram_route(1)
     xr = x.astype(np.complex128)
     Gr = oracle.gram(xr, kd, lo, hi)
     H = oracle.hankel_matrix(np.abs(xr), kd, lo, hi)
