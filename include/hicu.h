@@ -210,6 +210,25 @@ int32_t hicu_line_search(const hicu_geom* geom, const void* g_dev, const double*
                          const void* F_dev, int32_t p, int32_t prec, double* eta_dev,
                          void* ws_dev, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * hicu_line_search without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and result as
+ * hicu_line_search; the workspace is a fixed device array inside the library
+ * (hicu_line_search_noalloc_max_bytes() = 64 MiB per GPU, held until the
+ * process ends), looked up once per device on the first call with that
+ * device current.  The call allocates nothing.  Problems whose line-search
+ * workspace (hicu_workspace_bytes without the residual Y) exceeds the
+ * scratch return HICU_ERR_WORKSPACE with nothing written.  Calls on one GPU
+ * share its scratch: calls that overlap in time on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.
+ * Profiling (hicu_profile_begin) does not time these calls.
+ * ------------------------------------------------------------------------ */
+size_t hicu_line_search_noalloc_max_bytes(void);
+int32_t hicu_line_search_noalloc(const hicu_geom* geom, const void* g_dev, const double* gnorm2_dev,
+                                 const void* F_dev, int32_t p, int32_t prec, double* eta_dev,
+                                 void* stream);
+
 /* x <- x - eta g over the whole array (Algorithm 1 update); eta read from
  * device memory.  Observed entries stay bit-identical because g is zero
  * there.  A zero or non-finite eta leaves x untouched (hicu_line_search

@@ -77,6 +77,9 @@ SIGNATURES = {
     "hicu_line_search": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "hicu_update": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hicu_line_search_noalloc_max_bytes": (c_size_t, []),
+    "hicu_line_search_noalloc": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                           c_void_p, c_void_p]),
     "hicu_profile_begin": (c_int32, []),
     "hicu_profile_end": (c_int32, [ctypes.POINTER(KernelStat), c_int32, ctypes.POINTER(c_int32)]),
     "hicu_batch_create": (c_int32, [ctypes.POINTER(BatchItem), c_int32, c_int32, ctypes.POINTER(c_void_p),

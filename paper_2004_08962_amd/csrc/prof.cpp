@@ -18,6 +18,7 @@ struct Rec {
 
 std::mutex mu;
 bool enabled = false;
+thread_local int suppressed = 0;
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
 
@@ -34,6 +35,9 @@ hipEvent_t get_event() {
 
 }  // namespace
 
+ProfSuppress::ProfSuppress() { ++suppressed; }
+ProfSuppress::~ProfSuppress() { --suppressed; }
+
 bool prof_on() {
   std::lock_guard<std::mutex> l(mu);
   return enabled;
@@ -41,6 +45,7 @@ bool prof_on() {
 
 ProfScope::ProfScope(const char* tag, hipStream_t st, double flops, double bytes)
     : tag_(tag), st_(st), flops_(flops), bytes_(bytes) {
+  if (suppressed) return;
   std::lock_guard<std::mutex> l(mu);
   if (!enabled) return;
   a_ = get_event();

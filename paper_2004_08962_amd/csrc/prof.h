@@ -7,6 +7,16 @@ namespace hicu {
 
 bool prof_on();
 
+// While an object of this type is alive, ProfScope records nothing on the
+// calling thread (for entry points that must not create events).
+class ProfSuppress {
+ public:
+  ProfSuppress();
+  ~ProfSuppress();
+  ProfSuppress(const ProfSuppress&) = delete;
+  ProfSuppress& operator=(const ProfSuppress&) = delete;
+};
+
 // Records a start event at construction and a stop event at destruction on
 // `st` when profiling is enabled; `flops`/`bytes` are the algorithmic work of
 // the bracketed launch.
