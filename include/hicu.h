@@ -72,7 +72,15 @@ typedef enum { HICU_FP32 = 0, HICU_BF16 = 1, HICU_BF16X3 = 2, HICU_FP16 = 3 } hi
  * kdims     rectangular kernel box; n = prod(kdims) * nchan taps.
  * lo, hi    region S = [lo, hi) per axis on which H is built (the centre-out
  *           box or the whole array); requires 0 <= lo, hi <= dims,
- *           hi - lo >= kdims.  Valid outputs u satisfy lo <= u <= hi - K. */
+ *           hi - lo >= kdims.  Valid outputs u satisfy lo <= u <= hi - K.
+ * wrap      bit a set: the convolution along axis a (of the ndim given) is
+ *           circular instead of valid (METHODS, Study II: circular along
+ *           time for 2-D+t).  That axis's region must be the whole axis
+ *           (lo = 0, hi = dims, kdims <= dims); every position is an output
+ *           and patch indices wrap modulo dims.  0 = all valid.  The batched
+ *           entry points and the autotuner refuse circular axes
+ *           (HICU_ERR_UNSUPPORTED), and so does hicu_gram's direct route
+ *           (route 0 or more than 32 coils). */
 typedef struct {
   int32_t ndim;
   int32_t nchan;
@@ -80,6 +88,7 @@ typedef struct {
   int32_t kdims[3];
   int64_t lo[3];
   int64_t hi[3];
+  int32_t wrap;
 } hicu_geom;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -228,6 +237,22 @@ size_t hicu_line_search_noalloc_max_bytes(void);
 int32_t hicu_line_search_noalloc(const hicu_geom* geom, const void* g_dev, const double* gnorm2_dev,
                                  const void* F_dev, int32_t p, int32_t prec, double* eta_dev,
                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Time-averaged initialisation (METHODS, Study II: the initial k-space is
+ * the time average; a phase-encoding point sampled in no frame is zero).
+ * Along `axis` (0-based among the ndim axes of geom, the time frames), every
+ * unobserved sample takes the mean of the observed samples of the same
+ * location and coil over all frames; locations observed in no frame stay
+ * zero; observed samples are copied unchanged.  Means are summed in FP64
+ * over increasing frame index and rounded to FP32 once.
+ * x0_dev    complex64 zero-filled observations; mask_dev uint8 [d0][d1][d2]
+ *           (required); x_out_dev complex64, may alias x0_dev.
+ * Only geom's dims and nchan are used (region, kernel and wrap are ignored
+ * but must form a valid geometry).
+ * ------------------------------------------------------------------------ */
+int32_t hicu_time_average_init(const hicu_geom* geom, int32_t axis, const void* x0_dev,
+                               const uint8_t* mask_dev, void* x_out_dev, void* stream);
 
 /* x <- x - eta g over the whole array (Algorithm 1 update); eta read from
  * device memory.  Observed entries stay bit-identical because g is zero

@@ -22,6 +22,9 @@ for calibrationless MRI"):
   matching (zero at observed locations), the closed-form exact line search
   and the alternating minimisation of Algorithm 1.
 * ``metrics``  — signal-to-error ratio as defined in the METHODS section.
+* ``init``     — the time-averaged initial k-space of the 2-D+t study.
+* Circular axes: the lifting and everything built on it take ``wrap``
+  flags for the circular convolution along time of the 2-D+t study.
 
 Parity status per function is listed in each module header.
 """
@@ -31,10 +34,11 @@ from .jl import philox4x32_10, philox_normals, jl_matrix
 from .descent import objective_grad, line_search, descent_step, solve, objective
 from .metrics import ser, rel_err
 from .pointwise import grad_at_points, residual_at_points, gram_entries
+from .init import time_average_init
 
 __all__ = [
     "valid_extent", "hankel_matrix", "hankel_adjoint", "forward", "adjoint", "gram",
     "nullspace", "philox4x32_10", "philox_normals", "jl_matrix", "objective_grad",
     "line_search", "descent_step", "solve", "objective", "ser", "rel_err",
-    "grad_at_points", "residual_at_points", "gram_entries",
+    "grad_at_points", "residual_at_points", "gram_entries", "time_average_init",
 ]

@@ -33,55 +33,56 @@ def _as_c128(a):
     return np.asarray(a, dtype=np.complex128)
 
 
-def objective(x, F, kdims, lo, hi):
+def objective(x, F, kdims, lo, hi, wrap=None):
     """J = ||H(x) F||_F^2 on region [lo, hi)."""
-    Y = hankel_matrix(_as_c128(x), kdims, lo, hi) @ _as_c128(F)
+    Y = hankel_matrix(_as_c128(x), kdims, lo, hi, wrap) @ _as_c128(F)
     return float(np.vdot(Y, Y).real)
 
 
-def objective_grad(x, mask, F, kdims, lo, hi):
+def objective_grad(x, mask, F, kdims, lo, hi, wrap=None):
     """Returns (J, g, ||g||^2) with g = 2 (1 - M) o H'(H(x) F F^H)."""
     x = _as_c128(x)
     F = _as_c128(F)
-    Y = hankel_matrix(x, kdims, lo, hi) @ F
+    Y = hankel_matrix(x, kdims, lo, hi, wrap) @ F
     J = float(np.vdot(Y, Y).real)
-    g = 2.0 * hankel_adjoint(Y @ F.conj().T, x.shape, kdims, lo, hi)
+    g = 2.0 * hankel_adjoint(Y @ F.conj().T, x.shape, kdims, lo, hi, wrap)
     if mask is not None:
         g[np.asarray(mask).astype(bool)] = 0.0
     return J, g, float(np.vdot(g, g).real)
 
 
-def line_search(g, F, gnorm2, kdims, lo, hi):
+def line_search(g, F, gnorm2, kdims, lo, hi, wrap=None):
     """Closed-form step eta = ||g||^2 / (2 ||H(g) F||^2) (0 when H(g) F = 0)."""
-    Z = hankel_matrix(_as_c128(g), kdims, lo, hi) @ _as_c128(F)
+    Z = hankel_matrix(_as_c128(g), kdims, lo, hi, wrap) @ _as_c128(F)
     zz = float(np.vdot(Z, Z).real)
     return 0.0 if zz == 0.0 else gnorm2 / (2.0 * zz)
 
 
-def descent_step(y, mask, F, kdims, lo, hi):
+def descent_step(y, mask, F, kdims, lo, hi, wrap=None):
     """One gradient step with exact line search; returns (y_new, J, gnorm2, eta)."""
-    J, g, gn2 = objective_grad(y, mask, F, kdims, lo, hi)
-    eta = line_search(g, F, gn2, kdims, lo, hi)
+    J, g, gn2 = objective_grad(y, mask, F, kdims, lo, hi, wrap)
+    eta = line_search(g, F, gn2, kdims, lo, hi, wrap)
     return _as_c128(y) - eta * g, J, gn2, eta
 
 
-def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, start_outer=0, trace=None):
+def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, start_outer=0, trace=None, wrap=None):
     """Algorithm 1 with the Gram-eigendecomposition nullspace route.
 
     ``schedule``: list of (lo, hi, steps) per outer iteration.  ``p == 0``
     uses the whole nullspace (F = Q); otherwise F = Q P^(i,j) with the JL
     matrix drawn for 0-based outer index i and inner index j.  Iterations
     before ``start_outer`` are skipped (resume from a saved x).  When
-    ``trace`` is a list, one dict per gradient step is appended.
+    ``trace`` is a list, one dict per gradient step is appended.  ``wrap``
+    flags circular axes (each outer region must then span those axes).
     """
     x = _as_c128(x0).copy()
     for i in range(start_outer, len(schedule)):
         lo, hi, steps = schedule[i]
-        Q, evals, _ = nullspace(gram(x, kdims, lo, hi), rank)
+        Q, evals, _ = nullspace(gram(x, kdims, lo, hi, wrap), rank)
         y = x
         for j in range(steps):
             F = Q if p == 0 else Q @ jl_matrix(seed, i, j, Q.shape[1], p)
-            y, J, gn2, eta = descent_step(y, mask, F, kdims, lo, hi)
+            y, J, gn2, eta = descent_step(y, mask, F, kdims, lo, hi, wrap)
             if trace is not None:
                 trace.append(dict(i=i, j=j, J=J, gnorm2=gn2, eta=eta,
                                   tail=float(evals[: Q.shape[1]].sum())))

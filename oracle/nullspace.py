@@ -20,9 +20,9 @@ import numpy as np
 from .hankel import hankel_matrix
 
 
-def gram(x, kdims, lo, hi):
+def gram(x, kdims, lo, hi, wrap=None):
     """G = H(x)' H(x), (n, n) Hermitian, complex128."""
-    H = hankel_matrix(np.asarray(x, np.complex128), kdims, lo, hi)
+    H = hankel_matrix(np.asarray(x, np.complex128), kdims, lo, hi, wrap)
     return H.conj().T @ H
 
 

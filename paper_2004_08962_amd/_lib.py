@@ -23,7 +23,7 @@ PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3}
 
 class Geom(ctypes.Structure):
     _fields_ = [("ndim", c_int32), ("nchan", c_int32), ("dims", c_int64 * 3), ("kdims", c_int32 * 3),
-                ("lo", c_int64 * 3), ("hi", c_int64 * 3)]
+                ("lo", c_int64 * 3), ("hi", c_int64 * 3), ("wrap", c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -77,6 +77,7 @@ SIGNATURES = {
     "hicu_line_search": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "hicu_update": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hicu_time_average_init": (c_int32, [ctypes.POINTER(Geom), c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "hicu_line_search_noalloc_max_bytes": (c_size_t, []),
     "hicu_line_search_noalloc": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                            c_void_p, c_void_p]),

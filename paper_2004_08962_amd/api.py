@@ -50,8 +50,15 @@ def _shape_checks(x_shape=None, kdims=None, F=None, mask=None, like=None, like_n
         raise ValueError("%s shape %s does not match x %s" % (like_name, tuple(like.shape), tuple(x_shape)))
 
 
-def geom(shape, kdims, lo=None, hi=None):
-    """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box."""
+def _wrap_bits(wrap):
+    if wrap is None:
+        return 0
+    return sum(1 << a for a in range(3) if wrap[a])
+
+
+def geom(shape, kdims, lo=None, hi=None, wrap=None):
+    """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box;
+    ``wrap``: three flags, circular convolution along those axes."""
     d = [int(v) for v in shape[:3]]
     g = Geom()
     g.ndim = 3
@@ -63,6 +70,7 @@ def geom(shape, kdims, lo=None, hi=None):
         g.kdims[a] = int(kdims[a])
         g.lo[a] = int(lo[a])
         g.hi[a] = int(hi[a])
+    g.wrap = _wrap_bits(wrap)
     return g
 
 
@@ -80,12 +88,12 @@ def num_taps(shape, kdims):
     return int(load().hicu_num_taps(ctypes.byref(geom(shape, kdims))))
 
 
-def gram(x, kdims, lo=None, hi=None):
+def gram(x, kdims, lo=None, hi=None, wrap=None):
     """G = H_S(x)' H_S(x) as complex128 (n, n)."""
     _shape_checks(x.shape)
     lib = load()
     _dev(x, torch.complex64, "x")
-    g = geom(x.shape, kdims, lo, hi)
+    g = geom(x.shape, kdims, lo, hi, wrap)
     n = int(lib.hicu_num_taps(ctypes.byref(g)))
     check(n, "hicu_num_taps")
     G = torch.empty((n, n), dtype=torch.complex128, device=x.device)
@@ -144,19 +152,19 @@ def set_filter_group_budget(nbytes):
     check(load().hicu_set_filter_group_budget(int(nbytes)), "hicu_set_filter_group_budget")
 
 
-def filter_group(shape, kdims, p, prec="fp32", lo=None, hi=None):
+def filter_group(shape, kdims, p, prec="fp32", lo=None, hi=None, wrap=None):
     """(filters per group of the gradient, whether Y is the compact BF16 residual)."""
     f, c = ctypes.c_int32(0), ctypes.c_int32(0)
-    check(load().hicu_filter_group(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec), ctypes.byref(f),
+    check(load().hicu_filter_group(ctypes.byref(geom(shape, kdims, lo, hi, wrap)), int(p), _prec(prec), ctypes.byref(f),
                                    ctypes.byref(c)), "hicu_filter_group")
     return int(f.value), bool(c.value)
 
 
-def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None):
-    return int(load().hicu_workspace_bytes(ctypes.byref(geom(shape, kdims, lo, hi)), int(p), _prec(prec)))
+def workspace_bytes(shape, kdims, p, prec="fp32", lo=None, hi=None, wrap=None):
+    return int(load().hicu_workspace_bytes(ctypes.byref(geom(shape, kdims, lo, hi, wrap)), int(p), _prec(prec)))
 
 
-def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=True, ws=None):
+def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=True, ws=None, wrap=None):
     """Returns (J, g, gnorm2): J and gnorm2 are 0-dim float64 CUDA tensors,
     g complex64 like x (None when want_grad is False)."""
     _shape_checks(x.shape, kdims, F, mask)
@@ -165,7 +173,7 @@ def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=T
     _dev(F, torch.complex64, "F")
     if mask is not None:
         _dev(mask, torch.uint8, "mask")
-    g = geom(x.shape, kdims, lo, hi)
+    g = geom(x.shape, kdims, lo, hi, wrap)
     p = F.shape[1]
     wsb = lib.hicu_workspace_bytes(ctypes.byref(g), p, _prec(prec))
     if wsb == 0:
@@ -179,7 +187,7 @@ def objective_grad(x, mask, F, kdims, lo=None, hi=None, prec="fp32", want_grad=T
     return J, gout, gn2
 
 
-def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None):
+def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None, wrap=None):
     """eta = ||g||^2 / (2 ||H(g) F||^2) as a 0-dim float64 CUDA tensor."""
     _shape_checks(gv.shape, kdims, F)
     if gnorm2.numel() != 1:
@@ -188,7 +196,7 @@ def line_search(gv, gnorm2, F, kdims, lo=None, hi=None, prec="fp32", ws=None):
     _dev(gv, torch.complex64, "g")
     _dev(F, torch.complex64, "F")
     _dev(gnorm2, torch.float64, "gnorm2")
-    g = geom(gv.shape, kdims, lo, hi)
+    g = geom(gv.shape, kdims, lo, hi, wrap)
     p = F.shape[1]
     wsb = lib.hicu_workspace_bytes(ctypes.byref(g), p, _prec(prec))
     ws = _workspace(wsb, gv.device) if ws is None else ws
@@ -213,7 +221,7 @@ def update(x, gv, eta, kdims=(1, 1, 1)):
 
 
 def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_steps=0, warm_start=True,
-          start_outer=0, out=None, ws=None, raise_nonfinite=True):
+          start_outer=0, out=None, ws=None, raise_nonfinite=True, wrap=None):
     """Algorithm 1 on the device.  ``schedule``: list of (lo, hi, steps).
     Returns (x, trace) with trace a list of dicts (one per gradient step).
     ``ws``: optional uint8 CUDA workspace of at least solve_workspace_bytes()
@@ -224,7 +232,7 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     _dev(x0, torch.complex64, "x0")
     if mask is not None:
         _dev(mask, torch.uint8, "mask")
-    g = geom(x0.shape, kdims)
+    g = geom(x0.shape, kdims, wrap=wrap)
     n_outer = len(schedule)
     steps = (ctypes.c_int32 * max(1, n_outer))(*[int(s[2]) for s in schedule])
     regs = (ctypes.c_int64 * max(1, 6 * n_outer))(
@@ -258,9 +266,9 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     return x, trace
 
 
-def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0):
+def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0, wrap=None):
     """Device bytes hicu_solve needs for this problem and schedule."""
-    g = geom(shape, kdims)
+    g = geom(shape, kdims, wrap=wrap)
     n_outer = len(schedule)
     steps = (ctypes.c_int32 * max(1, n_outer))(*[int(s[2]) for s in schedule])
     regs = (ctypes.c_int64 * max(1, 6 * n_outer))(
@@ -271,6 +279,23 @@ def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine
     prm.regions = ctypes.cast(regs, ctypes.POINTER(ctypes.c_int64))
     prm.prec, prm.refine_steps = _prec(prec), int(refine_steps)
     return int(load().hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm)))
+
+
+def time_average_init(x0, mask, axis=0, out=None):
+    """Study II initialisation: unobserved samples take the mean over frames
+    (axis ``axis`` of (D0, D1, D2)) of the observed samples at the same
+    location and coil; locations never observed stay zero."""
+    _shape_checks(x0.shape, mask=mask, like=out, like_name="out")
+    if mask is None:
+        raise ValueError("time_average_init needs the sampling mask")
+    lib = load()
+    _dev(x0, torch.complex64, "x0")
+    _dev(mask, torch.uint8, "mask")
+    out = torch.empty_like(x0) if out is None else _dev(out, torch.complex64, "out")
+    g = geom(x0.shape, (1, 1, 1))
+    check(lib.hicu_time_average_init(ctypes.byref(g), int(axis), _ptr(x0), _ptr(mask), _ptr(out), _stream()),
+          "hicu_time_average_init")
+    return out
 
 
 def profile_begin():

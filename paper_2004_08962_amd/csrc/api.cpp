@@ -23,21 +23,25 @@ int32_t make_geo(const hicu_geom* gm, Geo* o) {
   const int nd = gm->ndim;
   if (nd < 1 || nd > 3 || gm->nchan < 1) return HICU_ERR_ARG;
   const int sh = 3 - nd;
+  if (gm->wrap < 0 || gm->wrap >= (1 << nd)) return HICU_ERR_ARG;
   for (int a = 0; a < 3; ++a) {
     if (a < sh) {
       o->d[a] = 1;
       o->k[a] = 1;
       o->lo[a] = 0;
       o->hi[a] = 1;
+      o->wrap[a] = 0;
     } else {
       o->d[a] = gm->dims[a - sh];
       o->k[a] = gm->kdims[a - sh];
       o->lo[a] = gm->lo[a - sh];
       o->hi[a] = gm->hi[a - sh];
+      o->wrap[a] = (gm->wrap >> (a - sh)) & 1;
     }
     if (o->d[a] < 1 || o->k[a] < 1 || o->k[a] > 64) return HICU_ERR_SHAPE;
     if (o->lo[a] < 0 || o->hi[a] > o->d[a] || o->hi[a] - o->lo[a] < o->k[a]) return HICU_ERR_SHAPE;
-    o->m[a] = o->hi[a] - o->lo[a] - o->k[a] + 1;
+    if (o->wrap[a] && (o->lo[a] != 0 || o->hi[a] != o->d[a])) return HICU_ERR_SHAPE;
+    o->m[a] = o->wrap[a] ? o->d[a] : o->hi[a] - o->lo[a] - o->k[a] + 1;
   }
   o->nc = gm->nchan;
   const int64_t n = (int64_t)o->k[0] * o->k[1] * o->k[2] * o->nc;
@@ -165,6 +169,16 @@ int32_t hicu_line_search(const hicu_geom* gm, const void* gv, const double* gn2,
   if (!gv || !gn2 || !F || !eta || !valid_prec(prec)) return HICU_ERR_ARG;
   if (p < 1 || p > 1 << 20) return HICU_ERR_RANK;
   return line_search_impl(g, gv, gn2, F, p, prec, eta, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t hicu_time_average_init(const hicu_geom* gm, int32_t axis, const void* x0, const uint8_t* mask, void* xout,
+                               void* stream) {
+  Geo g;
+  HICU_TRY(make_geo(gm, &g));
+  if (!x0 || !mask || !xout || axis < 0 || axis >= gm->ndim) return HICU_ERR_ARG;
+  ProfScope ps("time_average", (hipStream_t)stream, 0.0, 16.0 * (double)g.npts * g.nc + (double)g.npts);
+  return launch_time_average(reinterpret_cast<const float2*>(x0), mask, reinterpret_cast<float2*>(xout), g.d,
+                             axis + (3 - gm->ndim), g.nc, (hipStream_t)stream);
 }
 
 int32_t hicu_update(const hicu_geom* gm, void* x, const void* gv, const double* eta, void* stream) {

@@ -33,6 +33,7 @@ struct Geo {
   int k[3];       // kernel box
   int64_t lo[3], hi[3];
   int64_t m[3];   // valid extents of region: hi - lo - k + 1
+  int wrap[3];    // 1: circular along this axis (whole axis, m = d)
   int64_t s;      // number of valid outputs
   int64_t npts;   // spatial points of the array
   int n;          // taps = k0 k1 k2 nc

@@ -12,7 +12,9 @@ namespace hicu {
 // and every real output column n in [col0, col0 + coutr):
 //   out[u, n] = scale * sum_{k in kernel box} sum_{e} in[org + u + k, e] * W[k, e, n]
 // where e runs over the real (re, im) entries of the input channels and
-// input points outside the validity box [vlo, vhi) read as zero.  Optional
+// input points outside the validity box [vlo, vhi) read as zero.  On an
+// axis with period wp > 0 the input index org + u + k is first wrapped into
+// [0, wp) (it lies within one period of that range).  Optional
 // epilogue: zero at masked positions, add to the existing output, and a
 // per-block sum of squares of the final values.
 struct ConvArgs {
@@ -30,6 +32,7 @@ struct ConvArgs {
   int h[3];               // halo extents
   int64_t vlo[3], vhi[3];
   int64_t org[3];
+  int64_t wp[3] = {0, 0, 0};  // circular axis: input index taken modulo wp (then checked against vlo/vhi)
   int64_t oe[3];          // output extents
   int64_t nt[3];          // tiles per axis
   int k[3];

@@ -83,6 +83,13 @@ __device__ __forceinline__ void stage_store(typename LdsElem<PREC>::T* hi, typen
 
 // V complex values from global memory at in + idx: nv = V loads them with
 // 16-byte loads, 0 < nv < V one by one (the rest zero), nv = 0 gives zeros.
+// Index on an axis of period P (0: not circular), for i within one period
+// of [0, P); the result is then checked against the validity box.
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t P) {
+  if (P == 0) return i;
+  return i < 0 ? i + P : (i >= P ? i - P : i);
+}
+
 template <int V>
 __device__ __forceinline__ void load_unit(const float2* in, int64_t idx, int nv, float (&v)[2 * V]) {
   if (nv == V) {
@@ -210,7 +217,9 @@ __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<
   uint32_t wv[SB][V];
   int loff[SB];
   auto fetch = [&](const int b, const int hh0, const int hh1, const int hh2, const int cq) {
-    const int64_t i0 = a.org[0] + base0 + hh0, i1 = a.org[1] + base1 + hh1, i2 = a.org[2] + base2 + hh2;
+    const int64_t i0 = wrap_index(a.org[0] + base0 + hh0, a.wp[0]);
+    const int64_t i1 = wrap_index(a.org[1] + base1 + hh1, a.wp[1]);
+    const int64_t i2 = wrap_index(a.org[2] + base2 + hh2, a.wp[2]);
     const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
                     i2 < a.vhi[2];
     const int nv = ok ? max(0, min(V, a.cin - (cbase + cq * V))) : 0;
@@ -534,9 +543,9 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
         const int q = pt / a.h[2];
         const int hh1 = q % a.h[1];
         const int hh0 = q / a.h[1];
-        const int64_t i0 = a.org[0] + base0 + hh0;
-        const int64_t i1 = a.org[1] + base1 + hh1;
-        const int64_t i2 = a.org[2] + base2 + hh2;
+        const int64_t i0 = wrap_index(a.org[0] + base0 + hh0, a.wp[0]);
+        const int64_t i1 = wrap_index(a.org[1] + base1 + hh1, a.wp[1]);
+        const int64_t i2 = wrap_index(a.org[2] + base2 + hh2, a.wp[2]);
         const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
                         i2 < a.vhi[2];
         goff[i] = ok ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] : -1;

@@ -231,18 +231,23 @@ void set_gram_route(int r) { g_route.store(r == 0 ? 0 : 1); }
 // Segments of one axis of the region [lo, lo + m + K - 1): with m >= K, K - 1
 // single planes, the core [lo + K - 1, lo + m) and K - 1 single planes, and
 // window k is segments [k, k + K); with m < K every plane is a segment and
-// window k is segments [k, k + m).
+// window k is segments [k, k + m).  A circular axis is one segment (the
+// whole axis, m = its extent) shared by every window.
 struct AxisSegs {
   int64_t lo, m;
   int K;
-  __host__ __device__ int count() const { return m >= K ? 2 * K - 1 : (int)(m + K - 1); }
+  int wrap;
+  __host__ __device__ int count() const { return wrap ? 1 : (m >= K ? 2 * K - 1 : (int)(m + K - 1)); }
   __host__ __device__ int64_t start(int j) const {
-    if (m < K) return lo + j;
+    if (wrap || m < K) return lo + j;
     return j < K ? lo + j : lo + m + (j - K);
   }
-  __host__ __device__ int64_t len(int j) const { return (m >= K && j == K - 1) ? m - K + 1 : 1; }
-  // segments of window k: [k, k + width())
-  __host__ __device__ int width() const { return m >= K ? K : (int)m; }
+  __host__ __device__ int64_t len(int j) const {
+    return wrap ? m : ((m >= K && j == K - 1) ? m - K + 1 : 1);
+  }
+  // segments of window k: [first(k), first(k) + width())
+  __host__ __device__ int first(int k) const { return wrap ? 0 : k; }
+  __host__ __device__ int width() const { return wrap ? 1 : (m >= K ? K : (int)m); }
 };
 
 struct CorrArgs {
@@ -250,6 +255,7 @@ struct CorrArgs {
   int64_t d1, d2;          // array extents of axes 1, 2
   int nc;
   int64_t lo[3], hi[3];    // region
+  int64_t per[3];          // period of a circular axis (its extent), 0 otherwise
   int K[3];
   AxisSegs ax[3];
   int ncell;
@@ -308,8 +314,9 @@ __host__ __device__ inline void shift_of(const CorrArgs& a, int h, int* d) {
 // and accumulates the T x T grid of 16 x 16 real-embedding tiles of
 // sum_w x[w] x[w + d]^T with v_mfma_f64_16x16x4 (4 points per step; lane
 // group g takes points g, g + 4, ...).  x[w + d] outside the region counts as
-// zero (such cell/shift pairs are never assembled).  Operands are fetched
-// kGramAhead steps ahead and widened to FP64 at use.
+// zero (such cell/shift pairs are never assembled); on a circular axis it
+// wraps.  Operands are fetched kGramAhead steps ahead and widened to FP64
+// at use.
 template <int T>
 __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int ngrp = (a.nd_half + 3) / 4;
@@ -327,7 +334,6 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   bool okc[T];
 #pragma unroll
   for (int i = 0; i < T; ++i) okc[i] = 16 * i + m < two_nc;
-  const int64_t dOff = ((int64_t)d[0] * a.d1 * a.d2 + (int64_t)d[1] * a.d2 + d[2]) * two_nc;
 
   double4_t acc[T][T];
 #pragma unroll
@@ -340,14 +346,17 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   auto fetch = [&](float (&av)[T], float (&bv)[T]) {
     const bool ok = q < q_end;
     const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
-    const int64_t v0 = w0 + d[0], v1 = w1 + d[1], v2 = w2 + d[2];
+    auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
+    const int64_t v0 = wrap_to(w0 + d[0], a.per[0]), v1 = wrap_to(w1 + d[1], a.per[1]),
+                  v2 = wrap_to(w2 + d[2], a.per[2]);
     const bool okb = ok && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] && v2 >= a.lo[2] &&
                      v2 < a.hi[2];
     const int64_t base = ok ? ((w0 * a.d1 + w1) * a.d2 + w2) * two_nc : 0;
+    const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
       av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
-      bv[i] = (okb && okc[i]) ? a.x[base + dOff + 16 * i + m] : 0.f;
+      bv[i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
     }
     q += 4;
     p2 += 4;
@@ -426,9 +435,10 @@ __global__ __launch_bounds__(256) void corr_assemble_kernel(CorrArgs a, int n, d
     double rr = 0.0, ii = 0.0, ri = 0.0, ir = 0.0;
     const int e_rr = (2 * c) * a.W + 2 * cp, e_ii = (2 * c + 1) * a.W + 2 * cp + 1;
     const int e_ri = (2 * c) * a.W + 2 * cp + 1, e_ir = (2 * c + 1) * a.W + 2 * cp;
-    for (int j0 = k0; j0 < k0 + wd0; ++j0)
-      for (int j1 = k1; j1 < k1 + wd1; ++j1)
-        for (int j2 = k2; j2 < k2 + wd2; ++j2) {
+    const int f0 = a.ax[0].first(k0), f1 = a.ax[1].first(k1), f2 = a.ax[2].first(k2);
+    for (int j0 = f0; j0 < f0 + wd0; ++j0)
+      for (int j1 = f1; j1 < f1 + wd1; ++j1)
+        for (int j2 = f2; j2 < f2 + wd2; ++j2) {
           const int cell = (j0 * n1 + j1) * n2 + j2;
           const int first = a.cell_ent[2 * cell], cnt = a.cell_ent[2 * cell + 1];
           const double* src =
@@ -469,6 +479,8 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
     a.ax[i].lo = g.lo[i];
     a.ax[i].m = g.m[i];
     a.ax[i].K = g.k[i];
+    a.ax[i].wrap = g.wrap[i];
+    a.per[i] = g.wrap[i] ? g.d[i] : 0;
   }
   a.ncell = a.ax[0].count() * a.ax[1].count() * a.ax[2].count();
   if (a.ncell > 65535) return false;  // the reduce launch puts cells on grid axis y
@@ -509,7 +521,8 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
 
 int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_bytes, hipStream_t st) {
   CorrPlan cp;
-  if (gram_route() == 1 && corr_plan(g, &cp)) {
+  const bool circular = g.wrap[0] || g.wrap[1] || g.wrap[2];
+  if ((gram_route() == 1 || circular) && corr_plan(g, &cp)) {
     if (ws == nullptr || ws_bytes < cp.total) return HICU_ERR_WORKSPACE;
     CorrArgs a = cp.a;
     char* b = reinterpret_cast<char*>(ws);
@@ -537,6 +550,7 @@ int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_by
     HICU_HIP_TRY(hipGetLastError());
     return HICU_OK;
   }
+  if (circular) return HICU_ERR_UNSUPPORTED;  // the direct route has no circular axes
   int ntile, ntri, ngroups;
   int64_t qper;
   gram_layout(g, &ntile, &ntri, &ngroups, &qper);

@@ -9,6 +9,9 @@ int32_t launch_jl(const float2* Q, int n, int nq, int p, uint64_t seed, uint32_t
 int32_t launch_eta(const double* part, int64_t count, const double* gnorm2, double* eta, hipStream_t st);
 int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t count, hipStream_t st);
 int32_t launch_zero(void* ptr, size_t bytes, hipStream_t st);
+// Time-averaged initialisation along canonical axis `axis` of extents d.
+int32_t launch_time_average(const float2* x0, const uint8_t* mask, float2* out, const int64_t d[3], int axis,
+                            int nc, hipStream_t st);
 // *out = number of non-finite values among the `count` floats at v.
 int32_t launch_count_nonfinite(const float* v, int64_t count, unsigned long long* out, hipStream_t st);
 

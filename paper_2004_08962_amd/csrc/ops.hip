@@ -121,6 +121,50 @@ int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t cou
   return HICU_OK;
 }
 
+// Time-averaged initialisation (METHODS, Study II): along axis t, each
+// (location, coil) column gets the mean of its observed samples at the
+// unobserved ones; a column observed in no frame stays zero.  One thread per
+// column; the points of a column are p = (o * nt + t) * inner + i.  Sums in
+// FP64 in increasing t, one rounding to FP32.  Each thread reads and writes
+// only its own column, so out may alias x0.
+__global__ __launch_bounds__(256) void time_average_kernel(const float2* x0, const uint8_t* mask, float2* out,
+                                                           int64_t outer, int64_t nt, int64_t inner, int nc) {
+  const int64_t cols = outer * inner * nc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cols; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nc);
+    const int64_t i = (e / nc) % inner, o = e / ((int64_t)nc * inner);
+    double sr = 0.0, si = 0.0;
+    int64_t cnt = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t p = (o * nt + t) * inner + i;
+      if (mask[p]) {
+        const float2 v = x0[p * nc + c];
+        sr += (double)v.x;
+        si += (double)v.y;
+        ++cnt;
+      }
+    }
+    const float2 avg = cnt ? make_float2((float)(sr / (double)cnt), (float)(si / (double)cnt)) : make_float2(0.f, 0.f);
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t p = (o * nt + t) * inner + i;
+      out[p * nc + c] = mask[p] ? x0[p * nc + c] : avg;
+    }
+  }
+}
+
+int32_t launch_time_average(const float2* x0, const uint8_t* mask, float2* out, const int64_t d[3], int axis,
+                            int nc, hipStream_t st) {
+  int64_t outer = 1, inner = 1;
+  for (int a = 0; a < axis; ++a) outer *= d[a];
+  for (int a = axis + 1; a < 3; ++a) inner *= d[a];
+  const int64_t cols = outer * inner * nc;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(cdiv(cols, 256), 16384));
+  hipLaunchKernelGGL(time_average_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x0, mask, out, outer, d[axis],
+                     inner, nc);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
 // Number of non-finite floats among v[0..count) added into *out (grid-stride,
 // one atomic per block).
 __global__ __launch_bounds__(256) void nonfinite_kernel(const float* v, int64_t count, unsigned long long* out) {

@@ -145,6 +145,7 @@ void fill_forward_args(const Geo& g, const void* in, StepPlan& sp, void* ws, flo
     a.vlo[i] = 0;
     a.vhi[i] = g.d[i];
     a.org[i] = g.lo[i];
+    a.wp[i] = g.wrap[i] ? g.d[i] : 0;
   }
   a.B = at(ws, sp.off_Bf);
   a.Blo = at(ws, sp.off_Bflo);
@@ -179,6 +180,7 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
     a.vlo[i] = 0;
     a.vhi[i] = g.m[i];
     a.org[i] = -(int64_t)(g.k[i] - 1);
+    a.wp[i] = g.wrap[i] ? g.m[i] : 0;
   }
   a.B = B;
   a.Blo = Blo;

@@ -47,6 +47,10 @@ WORKLOADS = {
     # 2-D+t cine: 25 frames of 160x144 x 12 coils, 5x5x5 kernel over (t, kx, ky).
     "cine_25x160x144x12": dict(dims=(25, 160, 144), nc=12, kdims=(5, 5, 5), rank=130, p=12,
                                outer=6, inner=5, co_outer=5, co_axes=(1, 2), seed=4),
+    # the same cine data with the study's circular time axis and time-averaged start
+    "cine_25x160x144x12_circ": dict(dims=(25, 160, 144), nc=12, kdims=(5, 5, 5), rank=130, p=12,
+                                    outer=6, inner=5, co_outer=5, co_axes=(1, 2), seed=4,
+                                    wrap=(True, False, False), init="time_average"),
     # 3-D knee-like volume 256x320x320 x 8 coils, 5x5x5 kernel, 900 nullspace filters.
     "3d_256x320x320x8": dict(dims=(256, 320, 320), nc=8, kdims=(5, 5, 5), rank=100, p=0,
                              outer=11, inner=5, last_inner=20, co_outer=10,
@@ -77,7 +81,7 @@ def _finish(name, w, x_true, mask):
     x0 = x_true * mask[..., None]
     return dict(name=name, x_true=x_true, mask=mask, x0=x0, kdims=tuple(w["kdims"]),
                 rank=int(w["rank"]), p=int(w["p"]), schedule=_schedule(w, dims),
-                seed=int(w["seed"]))
+                seed=int(w["seed"]), wrap=w.get("wrap"), init=w.get("init", "zero"))
 
 
 def make_problem(name, dtype=np.complex128):
@@ -99,7 +103,7 @@ def make_problem(name, dtype=np.complex128):
         x = add_noise(to_kspace(img, maps), 30.0, rng)[None]
         lines = vd_lines(shp[1], int(round(shp[1] / 4)), 16, rng)
         mask = line_mask(dims, 2, lines)
-    elif name == "cine_25x160x144x12":
+    elif name.startswith("cine_25x160x144x12"):
         nt, nx, ny = dims
         imgs = cine_phantom(nt, (nx, ny), 6, rng)
         maps = gaussian_coil_maps((nx, ny), nc, rng)

@@ -39,39 +39,39 @@ def _ops_factor(prec, terms):
     return 2.0 * u + u * u + terms * U32
 
 
-def forward_bound(x, F, kd, lo, hi, prec):
+def forward_bound(x, F, kd, lo, hi, prec, wrap=None):
     """Elementwise bound on |Y_gpu - Y| for Y = H(x) F; also returns Y."""
     n = F.shape[0]
-    Y = oracle.forward(x, F, kd, lo, hi)
-    Yabs = oracle.forward(np.abs(x), np.abs(F), kd, lo, hi).real
+    Y = oracle.forward(x, F, kd, lo, hi, wrap)
+    Yabs = oracle.forward(np.abs(x), np.abs(F), kd, lo, hi, wrap).real
     b = _ops_factor(prec, 2 * n + 2) * Yabs
     if prec == "fp16":
         sx = f16_scale(float(np.max(np.abs(x))), margin=0)
-        rows = oracle.forward(np.abs(x), np.ones((n, 1)), kd, lo, hi).real  # sum_i |H[u, i]|
+        rows = oracle.forward(np.abs(x), np.ones((n, 1)), kd, lo, hi, wrap).real  # sum_i |H[u, i]|
         cols = np.sum(np.abs(F), axis=0)[None, :]                           # sum_i |F[i, j]|
         b = b + 2.0 * F16_SUB * (cols / sx + rows)
     return Y, b
 
 
-def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1):
+def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1, wrap=None):
     """Elementwise bound on |g_gpu - g| for g = 2 (1-M) o H'(Y F^H), with the
     propagated error of the stored Y (rounded to FP32) included.  An adjoint
     summed over `groups` filter groups adds one FP32 rounding per group."""
     p = F.shape[1]
     K = kd[0] * kd[1] * kd[2]
-    Y, eY = forward_bound(x, F, kd, lo, hi, prec)
+    Y, eY = forward_bound(x, F, kd, lo, hi, prec, wrap)
     eY = eY + U32 * np.abs(Y)
     Fa = np.abs(F)
     shape = x.shape
-    prop = 2.0 * oracle.hankel_adjoint(eY @ Fa.T, shape, kd, lo, hi).real
-    mag = 2.0 * oracle.hankel_adjoint(np.abs(Y) @ Fa.T, shape, kd, lo, hi).real
+    prop = 2.0 * oracle.hankel_adjoint(eY @ Fa.T, shape, kd, lo, hi, wrap).real
+    mag = 2.0 * oracle.hankel_adjoint(np.abs(Y) @ Fa.T, shape, kd, lo, hi, wrap).real
     b = prop + _ops_factor(prec, 2 * K * p + 2 + groups) * mag
     if prec == "fp16":
         n = F.shape[0]
         sy = f16_scale(float(np.max(np.abs(Y))))
         ones_s = np.ones((Y.shape[0], p))
-        fsum = oracle.hankel_adjoint(ones_s @ Fa.T, shape, kd, lo, hi).real          # sum over taps, filters of |F|
-        ysum = oracle.hankel_adjoint(np.abs(Y) @ np.ones((p, n)), shape, kd, lo, hi).real  # of |Y|
+        fsum = oracle.hankel_adjoint(ones_s @ Fa.T, shape, kd, lo, hi, wrap).real          # sum over taps, filters of |F|
+        ysum = oracle.hankel_adjoint(np.abs(Y) @ np.ones((p, n)), shape, kd, lo, hi, wrap).real  # of |Y|
         b = b + 2.0 * 2.0 * F16_SUB * (fsum / sy + ysum)
     if mask is not None:
         b[np.asarray(mask).astype(bool)] = 0.0

@@ -127,3 +127,25 @@ def test_solve_workspace_is_the_callers(lib):
     assert lib.hicu_solve(ctypes.byref(g), fake, None, ctypes.byref(bad), fake, None, fake, b, None) == -3
     badp, keep3 = _params(prec=9)
     assert lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(badp)) == 0
+
+
+def test_circular_axis_validation(lib):
+    """A circular axis must span the whole array, and wrap bits must name
+    given axes; both are refused before any launch."""
+    g = _geom(dims=(9, 21, 19), nc=3, k=(3, 3, 3))
+    g.wrap = 1
+    assert lib.hicu_num_outputs(ctypes.byref(g)) == 9 * 19 * 17   # every frame is an output
+    g.lo[0], g.hi[0] = 1, 9
+    assert lib.hicu_num_taps(ctypes.byref(g)) == -2
+    g2 = _geom(dims=(1, 40, 30), nc=2, k=(1, 5, 5))
+    g2.ndim = 2
+    g2.dims[0], g2.dims[1], g2.kdims[0], g2.kdims[1] = 40, 30, 5, 5
+    g2.lo[0] = g2.lo[1] = 0
+    g2.hi[0], g2.hi[1] = 40, 30
+    g2.wrap = 4  # bit 2 names no axis of a 2-D geometry
+    assert lib.hicu_num_taps(ctypes.byref(g2)) == -1
+    g2.wrap = 2  # second given axis circular
+    assert lib.hicu_num_outputs(ctypes.byref(g2)) == 36 * 30
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.hicu_time_average_init(ctypes.byref(g2), 2, fake, fake, fake, None) == -1
+    assert lib.hicu_time_average_init(ctypes.byref(g2), 0, fake, None, fake, None) == -1
