@@ -80,7 +80,18 @@ typedef enum { HICU_FP32 = 0, HICU_BF16 = 1, HICU_BF16X3 = 2, HICU_FP16 = 3 } hi
  *           and patch indices wrap modulo dims.  0 = all valid.  The batched
  *           entry points and the autotuner refuse circular axes
  *           (HICU_ERR_UNSUPPORTED), and so does hicu_gram's direct route
- *           (route 0 or more than 32 coils). */
+ *           (route 0 or more than 32 coils).
+ * kmask     HOST pointer to prod(kdims) bytes (row-major over the kernel box,
+ *           0 / nonzero) giving the support of the annihilating kernels
+ *           (THEORY: the {0,1} kernel mask; DISCUSSION: circular or
+ *           spherical supports), or NULL for the whole box.  The taps are
+ *           the offsets with nonzero mask in lexicographic order, coil
+ *           fastest, so n = (number of nonzero entries) * nchan; F, G and Q
+ *           use that tap order.  The contractions run on the bounding box
+ *           with zero weights outside the mask; the Gram is the box Gram
+ *           restricted to the mask's taps.  Boxes of up to 512 offsets; the
+ *           batched entry points and the autotuner refuse masks
+ *           (HICU_ERR_UNSUPPORTED).  Read during the call only. */
 typedef struct {
   int32_t ndim;
   int32_t nchan;
@@ -89,6 +100,7 @@ typedef struct {
   int64_t lo[3];
   int64_t hi[3];
   int32_t wrap;
+  const uint8_t* kmask;
 } hicu_geom;
 
 /* Library version (major*10000 + minor*100 + patch). */

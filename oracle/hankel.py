@@ -14,6 +14,11 @@ Conventions (readings recorded with the project's design notes):
   (k0, k1, k2, c) with the coil c fastest.
 * H[u, (k, c)] = x[u + k, c]: a correlation (no kernel flip, no conjugate).
   A flip would only permute the n columns; nothing observable changes.
+* Kernel mask (THEORY: the {0,1} mask K marks the support of an
+  annihilating kernel; DISCUSSION: circular or spherical supports): pass
+  ``kdims`` as a 3-D boolean array instead of a box; the columns are then
+  the taps k with K[k] = 1, in lexicographic order of k, coil fastest, and
+  the valid extent follows the bounding box K.shape.
 * Circular axes (METHODS, Study II: the convolution along time is circular
   rather than valid): on an axis flagged in ``wrap`` the region must be the
   whole axis, every position is an output (m = N) and the patch index
@@ -29,9 +34,18 @@ def _wrap3(wrap):
     return (False, False, False) if wrap is None else tuple(bool(w) for w in wrap)
 
 
+def kernel_box(kdims):
+    """(box extents, tap offsets in lexicographic order) of a box or mask."""
+    if isinstance(kdims, np.ndarray) and kdims.ndim == 3:
+        return tuple(int(v) for v in kdims.shape), [tuple(int(v) for v in t) for t in np.argwhere(kdims)]
+    K = tuple(int(v) for v in kdims)
+    return K, [(a, b, c) for a in range(K[0]) for b in range(K[1]) for c in range(K[2])]
+
+
 def valid_extent(lo, hi, kdims, wrap=None):
     """Number of outputs per axis: hi - lo - K + 1 (valid), hi - lo (circular)."""
     wrap = _wrap3(wrap)
+    kdims = kernel_box(kdims)[0]
     m = tuple(int(h) - int(l) - (0 if w else int(k) - 1) for l, h, k, w in zip(lo, hi, kdims, wrap))
     if any(v <= 0 for v in m) or any(w and k > h - l for l, h, k, w in zip(lo, hi, kdims, wrap)):
         raise ValueError("region smaller than kernel: lo=%s hi=%s K=%s" % (lo, hi, kdims))
@@ -52,7 +66,7 @@ def _window(lo, k, m, shape, wrap):
 
 
 def _offsets(kdims):
-    return [(a, b, c) for a in range(kdims[0]) for b in range(kdims[1]) for c in range(kdims[2])]
+    return kernel_box(kdims)[1]
 
 
 def hankel_matrix(x, kdims, lo, hi, wrap=None):

@@ -23,7 +23,7 @@ PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3}
 
 class Geom(ctypes.Structure):
     _fields_ = [("ndim", c_int32), ("nchan", c_int32), ("dims", c_int64 * 3), ("kdims", c_int32 * 3),
-                ("lo", c_int64 * 3), ("hi", c_int64 * 3), ("wrap", c_int32)]
+                ("lo", c_int64 * 3), ("hi", c_int64 * 3), ("wrap", c_int32), ("kmask", c_void_p)]
 
 
 class Params(ctypes.Structure):

@@ -30,6 +30,13 @@ def _dev(t, dtype, name):
     return t
 
 
+def _taps(kdims):
+    """Taps of a kernel box (3 extents) or of a kernel mask (3-D array)."""
+    if hasattr(kdims, "ndim") and kdims.ndim == 3:
+        return int((kdims != 0).sum())
+    return int(kdims[0]) * int(kdims[1]) * int(kdims[2])
+
+
 def _shape_checks(x_shape=None, kdims=None, F=None, mask=None, like=None, like_name="g"):
     """Shape agreement between the arguments, checked before any device
     pointer is handed to the library (a mismatched buffer would be read or
@@ -40,10 +47,10 @@ def _shape_checks(x_shape=None, kdims=None, F=None, mask=None, like=None, like_n
         if F.dim() != 2:
             raise ValueError("F must be 2-D (n, p), got %s" % (tuple(F.shape),))
         if x_shape is not None and kdims is not None:
-            n = int(kdims[0]) * int(kdims[1]) * int(kdims[2]) * int(x_shape[3])
+            n = _taps(kdims) * int(x_shape[3])
             if F.shape[0] != n:
-                raise ValueError("F has %d rows; the kernel %s over %d coils has %d taps"
-                                 % (F.shape[0], tuple(kdims), int(x_shape[3]), n))
+                raise ValueError("F has %d rows; the kernel over %d coils has %d taps"
+                                 % (F.shape[0], int(x_shape[3]), n))
     if mask is not None and x_shape is not None and tuple(mask.shape) != tuple(x_shape[:3]):
         raise ValueError("mask shape %s does not match k-space %s" % (tuple(mask.shape), tuple(x_shape[:3])))
     if like is not None and x_shape is not None and tuple(like.shape) != tuple(x_shape):
@@ -57,10 +64,17 @@ def _wrap_bits(wrap):
 
 
 def geom(shape, kdims, lo=None, hi=None, wrap=None):
-    """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box;
-    ``wrap``: three flags, circular convolution along those axes."""
+    """hicu_geom for x of shape (D0, D1, D2, Nc) and a 3-axis kernel box, or a
+    3-D kernel mask array (nonzero = tap, the box is its shape); ``wrap``:
+    three flags, circular convolution along those axes."""
+    import numpy as np
     d = [int(v) for v in shape[:3]]
     g = Geom()
+    if hasattr(kdims, "ndim") and kdims.ndim == 3:
+        km = np.ascontiguousarray(np.asarray(kdims) != 0, dtype=np.uint8)
+        g._kmask_ref = km  # kept alive with the struct
+        g.kmask = km.ctypes.data
+        kdims = km.shape
     g.ndim = 3
     g.nchan = int(shape[3])
     lo = (0, 0, 0) if lo is None else lo

@@ -44,13 +44,38 @@ int32_t make_geo(const hicu_geom* gm, Geo* o) {
     o->m[a] = o->wrap[a] ? o->d[a] : o->hi[a] - o->lo[a] - o->k[a] + 1;
   }
   o->nc = gm->nchan;
-  const int64_t n = (int64_t)o->k[0] * o->k[1] * o->k[2] * o->nc;
+  const int64_t box = (int64_t)o->k[0] * o->k[1] * o->k[2];
+  const int64_t n = box * o->nc;
   if (n > 16384) return HICU_ERR_SHAPE;
   o->n = (int)n;
+  o->nbox = (int)n;
+  o->kmasked = 0;
+  for (int w = 0; w < 8; ++w) o->kbits[w] = 0;
+  if (gm->kmask) {
+    if (box > 512) return HICU_ERR_UNSUPPORTED;
+    int taps = 0;
+    for (int64_t f = 0; f < box; ++f)
+      if (gm->kmask[f]) {
+        o->kbits[f >> 6] |= 1ull << (f & 63);
+        ++taps;
+      }
+    if (taps == 0) return HICU_ERR_SHAPE;
+    if (taps < box) {
+      o->kmasked = 1;
+      o->n = taps * o->nc;
+    }
+  }
   o->s = o->m[0] * o->m[1] * o->m[2];
   o->npts = o->d[0] * o->d[1] * o->d[2];
   if (o->npts > ((int64_t)1 << 40)) return HICU_ERR_SHAPE;
   return HICU_OK;
+}
+
+Geo box_geo(const Geo& g) {
+  Geo b = g;
+  b.kmasked = 0;
+  b.n = g.nbox;
+  return b;
 }
 
 }  // namespace hicu

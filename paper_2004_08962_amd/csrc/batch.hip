@@ -197,7 +197,8 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
   for (int q = 0; q < count; ++q) {
     BatchProblem& P = b->probs[q];
     HICU_TRY(make_geo(&items[q].geom, &P.g));
-    if (P.g.wrap[0] || P.g.wrap[1] || P.g.wrap[2]) return HICU_ERR_UNSUPPORTED;  // circular axes: single-problem calls only
+    if (P.g.wrap[0] || P.g.wrap[1] || P.g.wrap[2] || P.g.kmasked)
+      return HICU_ERR_UNSUPPORTED;  // circular axes, kernel masks: single-problem calls only
     if (!items[q].x || !items[q].Q || !items[q].scalars) return HICU_ERR_ARG;
     if (items[q].nq < 1 || items[q].nq >= P.g.n + 1 || items[q].p < 1 || items[q].p > items[q].nq)
       return HICU_ERR_RANK;

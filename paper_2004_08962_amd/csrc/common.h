@@ -34,12 +34,38 @@ struct Geo {
   int64_t lo[3], hi[3];
   int64_t m[3];   // valid extents of region: hi - lo - k + 1
   int wrap[3];    // 1: circular along this axis (whole axis, m = d)
+  int kmasked;    // 1: taps restricted to the set bits of kbits (box offsets, lexicographic)
+  uint64_t kbits[8];
+  int nbox;       // taps of the whole box k0 k1 k2 nc (= n when not masked)
   int64_t s;      // number of valid outputs
   int64_t npts;   // spatial points of the array
   int n;          // taps = k0 k1 k2 nc
 };
 
 int32_t make_geo(const hicu_geom* g, Geo* out);
+// The same geometry over the whole kernel box (no mask).
+Geo box_geo(const Geo& g);
+// Device helpers for kernel masks: box offset of the t-th tap, and the tap
+// number of box offset f (-1 when f is outside the mask).
+__host__ __device__ inline int kmask_tap_of(const uint64_t* bits, int f) {
+  if (!((bits[f >> 6] >> (f & 63)) & 1ull)) return -1;
+  int t = 0;
+  for (int w = 0; w < (f >> 6); ++w) t += __builtin_popcountll(bits[w]);
+  const uint64_t low = (f & 63) ? (bits[f >> 6] & ((1ull << (f & 63)) - 1ull)) : 0ull;
+  return t + __builtin_popcountll(low);
+}
+__host__ __device__ inline int kmask_offset_of(const uint64_t* bits, int t) {
+  for (int w = 0; w < 8; ++w) {
+    const int c = __builtin_popcountll(bits[w]);
+    if (t < c) {
+      uint64_t v = bits[w];
+      for (int i = 0; i < t; ++i) v &= v - 1ull;  // drop the t lowest set bits
+      return 64 * w + __builtin_ctzll(v);
+    }
+    t -= c;
+  }
+  return -1;
+}
 
 // ---------------------------------------------------------------------------
 // Precision modes of the contraction kernels

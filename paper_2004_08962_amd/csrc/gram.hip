@@ -310,23 +310,35 @@ __host__ __device__ inline void shift_of(const CorrArgs& a, int h, int* d) {
   d[0] = dl / (w2 * w1) - (a.K[0] - 1);
 }
 
-// Workgroup = (entry, group of 4 shifts); wave v takes shift 4 * group + v
-// and accumulates the T x T grid of 16 x 16 real-embedding tiles of
-// sum_w x[w] x[w + d]^T with v_mfma_f64_16x16x4 (4 points per step; lane
-// group g takes points g, g + 4, ...).  x[w + d] outside the region counts as
-// zero (such cell/shift pairs are never assembled); on a circular axis it
-// wraps.  Operands are fetched kGramAhead steps ahead and widened to FP64
-// at use.
+// Shifts per wave: a wave loads its points' components once and pairs them
+// with the shifted points of DW shifts, so narrow coil counts (T = 1, 2)
+// issue several MFMAs per operand load.
+__host__ __device__ constexpr int corr_dw(int T) { return T == 1 ? 4 : (T == 2 ? 2 : 1); }
+__host__ __device__ inline int corr_groups(int nd_half, int T) { return (nd_half + 4 * corr_dw(T) - 1) / (4 * corr_dw(T)); }
+
+// Workgroup = (entry, group of 4 DW shifts); wave v takes the DW shifts from
+// (4 group + v) DW and accumulates, for each, the T x T grid of 16 x 16
+// real-embedding tiles of sum_w x[w] x[w + d]^T with v_mfma_f64_16x16x4
+// (4 points per step; lane group g takes points g, g + 4, ...).  x[w + d]
+// outside the region counts as zero (such cell/shift pairs are never
+// assembled); on a circular axis it wraps.  Operands are fetched kGramAhead
+// steps ahead and widened to FP64 at use.
 template <int T>
 __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
-  const int ngrp = (a.nd_half + 3) / 4;
+  constexpr int DW = corr_dw(T);
+  const int ngrp = corr_groups(a.nd_half, T);
   const int64_t lin = gram_remap(blockIdx.x, (int64_t)a.nent * ngrp);
   const int ent = (int)(lin / ngrp), grp = (int)(lin % ngrp);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
-  const int h = grp * 4 + wave;
-  if (h >= a.nd_half) return;
-  int d[3];
-  shift_of(a, h, d);
+  const int h0 = (grp * 4 + wave) * DW;
+  if (h0 >= a.nd_half) return;
+  int d[DW][3];
+  bool hok[DW];
+#pragma unroll
+  for (int u = 0; u < DW; ++u) {
+    hok[u] = h0 + u < a.nd_half;
+    shift_of(a, hok[u] ? h0 + u : h0, d[u]);
+  }
   int64_t cst[3], cln[3];
   cell_box(a, a.ent_cell[ent], cst, cln);
   const int64_t q_begin = a.ent_q[2 * ent], q_end = a.ent_q[2 * ent + 1];
@@ -335,28 +347,32 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
   for (int i = 0; i < T; ++i) okc[i] = 16 * i + m < two_nc;
 
-  double4_t acc[T][T];
+  double4_t acc[DW][T][T];
 #pragma unroll
-  for (int i = 0; i < T; ++i)
+  for (int u = 0; u < DW; ++u)
 #pragma unroll
-    for (int j = 0; j < T; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int j = 0; j < T; ++j) acc[u][i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
   int64_t q = q_begin + g;
   int64_t p2 = q % cln[2], p1 = (q / cln[2]) % cln[1], p0 = q / (cln[2] * cln[1]);
-  auto fetch = [&](float (&av)[T], float (&bv)[T]) {
+  auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
+  auto fetch = [&](float (&av)[T], float (&bv)[DW][T]) {
     const bool ok = q < q_end;
     const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
-    auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
-    const int64_t v0 = wrap_to(w0 + d[0], a.per[0]), v1 = wrap_to(w1 + d[1], a.per[1]),
-                  v2 = wrap_to(w2 + d[2], a.per[2]);
-    const bool okb = ok && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] && v2 >= a.lo[2] &&
-                     v2 < a.hi[2];
     const int64_t base = ok ? ((w0 * a.d1 + w1) * a.d2 + w2) * two_nc : 0;
-    const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
 #pragma unroll
-    for (int i = 0; i < T; ++i) {
-      av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
-      bv[i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
+    for (int i = 0; i < T; ++i) av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
+#pragma unroll
+    for (int u = 0; u < DW; ++u) {
+      const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
+                    v2 = wrap_to(w2 + d[u][2], a.per[2]);
+      const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
+                       v2 >= a.lo[2] && v2 < a.hi[2];
+      const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+#pragma unroll
+      for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
     }
     q += 4;
     p2 += 4;
@@ -369,34 +385,42 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
     }
   };
   constexpr int PF = kGramAhead;
-  float av[PF][T], bv[PF][T];
+  float av[PF][T], bv[PF][DW][T];
 #pragma unroll
   for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
   for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
       if (q0 + 4 * r >= q_end) break;
-      double ad[T], bd[T];
+      double ad[T];
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        ad[i] = (double)av[r][i];
-        bd[i] = (double)bv[r][i];
+      for (int i = 0; i < T; ++i) ad[i] = (double)av[r][i];
+#pragma unroll
+      for (int u = 0; u < DW; ++u) {
+        double bd[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) bd[j] = (double)bv[r][u][j];
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int j = 0; j < T; ++j)
+            acc[u][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[u][i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < T; ++i)
-#pragma unroll
-        for (int j = 0; j < T; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[i][j], 0, 0, 0);
       fetch(av[r], bv[r]);  // the step PF positions further on
     }
   }
   // v_mfma_f64_16x16x4: lane holds rows g, g + 4, g + 8, g + 12 of column m
-  double* out = a.part + ((size_t)ent * a.nd_half + h) * a.ne;
 #pragma unroll
-  for (int i = 0; i < T; ++i)
+  for (int u = 0; u < DW; ++u) {
+    if (!hok[u]) continue;
+    double* out = a.part + ((size_t)ent * a.nd_half + h0 + u) * a.ne;
 #pragma unroll
-    for (int j = 0; j < T; ++j)
+    for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[(16 * i + g + 4 * r) * a.W + 16 * j + m] = acc[i][j][r];
+      for (int j = 0; j < T; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(16 * i + g + 4 * r) * a.W + 16 * j + m] = acc[u][i][j][r];
+  }
 }
 
 // Cells split over several entries: their partial sums added in entry order.
@@ -489,7 +513,9 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
   a.W = 16 * p->T;
   a.ne = a.W * a.W;
   const int64_t npts = region_points(g);
-  a.chunk = std::max<int64_t>(2048, std::min<int64_t>(131072, rup(npts / 64, 4)));
+  // entries sized for about 2048 heavy workgroups (several waves per SIMD to
+  // hide the operand loads), at least 512 points each
+  a.chunk = std::max<int64_t>(512, std::min<int64_t>(131072, rup(npts * corr_groups(a.nd_half, p->T) / 2048, 4)));
   int64_t nent = 0, multi = 0;
   for (int c = 0; c < a.ncell; ++c) {
     int64_t st[3], ln[3];
@@ -498,7 +524,7 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
     nent += k;
     multi += k > 1;
   }
-  const int64_t ngrp = (a.nd_half + 3) / 4;
+  const int64_t ngrp = corr_groups(a.nd_half, p->T);
   if (nent > (1 << 24) || nent * ngrp > 0x7fffffffLL) return false;
   a.nent = (int)nent;
   const size_t per = (size_t)a.nd_half * a.ne * sizeof(double);
@@ -519,7 +545,40 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
 
 }  // namespace
 
+// Kernel mask: G[i][j] = Gbox[box(i)][box(j)], box(t c) = (box offset of
+// tap t) nc + c.
+struct KBits {
+  uint64_t w[8];
+};
+__global__ __launch_bounds__(256) void gram_select_kernel(const double2* Gbox, int nbox, KBits bits, int nc, int n,
+                                                          double2* G) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const int bi = kmask_offset_of(bits.w, i / nc) * nc + i % nc;
+    const int bj = kmask_offset_of(bits.w, j / nc) * nc + j % nc;
+    G[e] = Gbox[(size_t)bi * nbox + bj];
+  }
+}
+
+static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, size_t ws_bytes, hipStream_t st);
+
 int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!g.kmasked) return launch_gram_box(g, x, G, ws, ws_bytes, st);
+  const Geo b = box_geo(g);
+  const size_t gb = al((size_t)g.nbox * g.nbox * sizeof(double2));
+  if (ws == nullptr || ws_bytes < gb) return HICU_ERR_WORKSPACE;
+  HICU_TRY(launch_gram_box(b, x, ws, at(ws, gb), ws_bytes - gb, st));
+  KBits kb;
+  for (int w = 0; w < 8; ++w) kb.w[w] = g.kbits[w];
+  const int64_t tot = (int64_t)g.n * g.n;
+  hipLaunchKernelGGL(gram_select_kernel, dim3((unsigned)std::min<int64_t>(cdiv(tot, 256), 16384)), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(ws), g.nbox, kb, g.nc, g.n, reinterpret_cast<double2*>(G));
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, size_t ws_bytes, hipStream_t st) {
   CorrPlan cp;
   const bool circular = g.wrap[0] || g.wrap[1] || g.wrap[2];
   if ((gram_route() == 1 || circular) && corr_plan(g, &cp)) {
@@ -533,7 +592,7 @@ int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_by
     a.part = reinterpret_cast<double*>(b + cp.off_part);
     a.cellsum = reinterpret_cast<double*>(b + cp.off_cellsum);
     hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(64), 0, st, a);
-    const int ngrp = (a.nd_half + 3) / 4;
+    const int ngrp = corr_groups(a.nd_half, cp.T);
     const dim3 grid((unsigned)((int64_t)a.nent * ngrp));
     switch (cp.T) {
       case 1: hipLaunchKernelGGL(corr_kernel<1>, grid, dim3(256), 0, st, a); break;
@@ -584,6 +643,7 @@ int32_t launch_gram(const Geo& g, const void* x, void* G, void* ws, size_t ws_by
 }
 
 size_t gram_workspace(const Geo& g) {
+  if (g.kmasked) return al((size_t)g.nbox * g.nbox * sizeof(double2)) + gram_workspace(box_geo(g));
   int ntile, ntri, ngroups;
   int64_t qper;
   gram_layout(g, &ntile, &ntri, &ngroups, &qper);

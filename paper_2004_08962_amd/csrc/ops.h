@@ -9,6 +9,12 @@ int32_t launch_jl(const float2* Q, int n, int nq, int p, uint64_t seed, uint32_t
 int32_t launch_eta(const double* part, int64_t count, const double* gnorm2, double* eta, hipStream_t st);
 int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t count, hipStream_t st);
 int32_t launch_zero(void* ptr, size_t bytes, hipStream_t st);
+struct KMaskBits {
+  uint64_t w[8];
+};
+// Spread filters over a kernel mask's taps (g.n rows) to the whole box
+// (g.nbox rows, zero outside the mask).
+int32_t launch_kmask_scatter(const Geo& g, const float2* F, int p, float2* Fbox, hipStream_t st);
 // Time-averaged initialisation along canonical axis `axis` of extents d.
 int32_t launch_time_average(const float2* x0, const uint8_t* mask, float2* out, const int64_t d[3], int axis,
                             int nc, hipStream_t st);

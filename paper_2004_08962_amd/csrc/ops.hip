@@ -121,6 +121,28 @@ int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t cou
   return HICU_OK;
 }
 
+// Kernel mask: filters over the mask's taps (n rows) spread to the whole
+// kernel box (nbox rows, zero rows outside the mask), p columns.
+__global__ __launch_bounds__(256) void kmask_scatter_kernel(const float2* F, KMaskBits bits, int nc, int nbox, int p,
+                                                            float2* Fbox) {
+  const int64_t total = (int64_t)nbox * p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / p), j = (int)(e % p);
+    const int t = kmask_tap_of(bits.w, row / nc);
+    Fbox[e] = t < 0 ? make_float2(0.f, 0.f) : F[((size_t)t * nc + row % nc) * p + j];
+  }
+}
+
+int32_t launch_kmask_scatter(const Geo& g, const float2* F, int p, float2* Fbox, hipStream_t st) {
+  KMaskBits kb;
+  for (int w = 0; w < 8; ++w) kb.w[w] = g.kbits[w];
+  const int64_t tot = (int64_t)g.nbox * p;
+  hipLaunchKernelGGL(kmask_scatter_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(tot, 256), 16384))),
+                     dim3(256), 0, st, F, kb, g.nc, g.nbox, p, Fbox);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
 // Time-averaged initialisation (METHODS, Study II): along axis t, each
 // (location, coil) column gets the mean of its observed samples at the
 // unobserved ones; a column observed in no frame stays zero.  One thread per

@@ -208,9 +208,19 @@ void fill_adjoint_args(const Geo& g, const void* Y, int p, const void* B, const 
 // adjoint launch of the group adds H_S'(Y_group F_group^H) into g.  The sum
 // over groups is the full adjoint because H_S'(Y F^H) is linear in the
 // filter columns; the last group writes the per-block sums of |g|^2.
+// Kernel masks: the filters are spread to the whole box (zero rows outside
+// the mask) at the head of the workspace and the step runs on the box.
+static size_t kmask_head(const Geo& g, int p) { return g.kmasked ? al((size_t)g.nbox * p * sizeof(float2)) : 0; }
+
 int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, const void* F, int p, int prec,
                             double* J, void* gout, double* gn2, void* ws, size_t ws_bytes, hipStream_t st,
                             int prep) {
+  if (g.kmasked) {
+    const size_t h = kmask_head(g, p);
+    if (!ws || ws_bytes < h) return HICU_ERR_WORKSPACE;
+    if (prep) HICU_TRY(launch_kmask_scatter(g, reinterpret_cast<const float2*>(F), p, reinterpret_cast<float2*>(ws), st));
+    return objective_grad_impl(box_geo(g), x, mask, ws, p, prec, J, gout, gn2, at(ws, h), ws_bytes - h, st, prep);
+  }
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, gout != nullptr, &sp));
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
@@ -316,6 +326,13 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
 
 int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
                          double* eta, void* ws, size_t ws_bytes, hipStream_t st, bool grad_weights) {
+  if (g.kmasked) {
+    const size_t h = kmask_head(g, p);
+    if (!ws || ws_bytes < h) return HICU_ERR_WORKSPACE;
+    if (!grad_weights)
+      HICU_TRY(launch_kmask_scatter(g, reinterpret_cast<const float2*>(F), p, reinterpret_cast<float2*>(ws), st));
+    return line_search_impl(box_geo(g), gv, gn2, ws, p, prec, eta, at(ws, h), ws_bytes - h, st, grad_weights);
+  }
   StepPlan sp;
   HICU_TRY(make_step_plan(g, p, prec, false, &sp));
   // The line-search layout is a prefix-compatible subset of the gradient
@@ -361,6 +378,10 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
 }
 
 size_t step_workspace(const Geo& g, int p, int prec) {
+  if (g.kmasked) {
+    const size_t inner = step_workspace(box_geo(g), p, prec);
+    return inner ? kmask_head(g, p) + inner : 0;
+  }
   StepPlan a, b;
   if (make_step_plan(g, p, prec, true, &a) != HICU_OK) return 0;
   if (make_step_plan(g, p, prec, false, &b) != HICU_OK) return 0;

@@ -182,7 +182,7 @@ int32_t hicu_autotune(const hicu_geom* gm, const void* x, const void* F, int32_t
   HICU_TRY(make_geo(gm, &g));
   if (!x || !F || !valid_prec(prec)) return HICU_ERR_ARG;
   if (p < 1 || p > 1 << 20) return HICU_ERR_RANK;
-  if (g.wrap[0] || g.wrap[1] || g.wrap[2]) return HICU_ERR_UNSUPPORTED;
+  if (g.wrap[0] || g.wrap[1] || g.wrap[2] || g.kmasked) return HICU_ERR_UNSUPPORTED;
   TuneEntry f, a;
   HICU_TRY(autotune(g, x, F, p, prec, ws, ws_bytes, (hipStream_t)stream, &f, &a));
   if (choice) {

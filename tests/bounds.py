@@ -58,7 +58,7 @@ def grad_bound(x, mask, F, kd, lo, hi, prec, groups=1, wrap=None):
     propagated error of the stored Y (rounded to FP32) included.  An adjoint
     summed over `groups` filter groups adds one FP32 rounding per group."""
     p = F.shape[1]
-    K = kd[0] * kd[1] * kd[2]
+    K = len(oracle.hankel.kernel_box(kd)[1])  # taps of the kernel box or mask
     Y, eY = forward_bound(x, F, kd, lo, hi, prec, wrap)
     eY = eY + U32 * np.abs(Y)
     Fa = np.abs(F)
@@ -87,7 +87,7 @@ def grad_bound_at_points(x, F, kd, lo, hi, prec, points, groups=1):
     """grad_bound evaluated only at k-space locations ``points`` (mask not
     applied), from the point-wise oracle routines on absolute values."""
     p = F.shape[1]
-    K = kd[0] * kd[1] * kd[2]
+    K = len(oracle.hankel.kernel_box(kd)[1])  # taps of the kernel box or mask
     n = F.shape[0]
     nc = x.shape[3]
     Fa = np.abs(F)

@@ -149,3 +149,26 @@ def test_circular_axis_validation(lib):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     assert lib.hicu_time_average_init(ctypes.byref(g2), 2, fake, fake, fake, None) == -1
     assert lib.hicu_time_average_init(ctypes.byref(g2), 0, fake, None, fake, None) == -1
+
+
+def test_kernel_mask_taps(lib):
+    """A kernel mask keeps the taps with nonzero entries; an all-ones mask is
+    the whole box; an empty or oversized one is refused."""
+    import numpy as np
+    g = _geom(dims=(1, 30, 30), nc=4, k=(1, 5, 5))
+    c = 2.0
+    a = np.arange(5)
+    disc = (((a[:, None] - c) ** 2 + (a[None, :] - c) ** 2) <= 6.25).astype(np.uint8)
+    g.kmask = disc.ctypes.data
+    assert lib.hicu_num_taps(ctypes.byref(g)) == int(disc.sum()) * 4
+    assert lib.hicu_num_outputs(ctypes.byref(g)) == 26 * 26
+    ones = np.ones(25, np.uint8)
+    g.kmask = ones.ctypes.data
+    assert lib.hicu_num_taps(ctypes.byref(g)) == 100
+    zeros = np.zeros(25, np.uint8)
+    g.kmask = zeros.ctypes.data
+    assert lib.hicu_num_taps(ctypes.byref(g)) == -2
+    big = _geom(dims=(20, 30, 30), nc=2, k=(9, 9, 9))
+    m9 = np.ones(729, np.uint8)
+    big.kmask = m9.ctypes.data
+    assert lib.hicu_num_taps(ctypes.byref(big)) == -7
