@@ -23,6 +23,9 @@ for calibrationless MRI"):
   and the alternating minimisation of Algorithm 1.
 * ``metrics``  — signal-to-error ratio as defined in the METHODS section.
 * ``init``     — the time-averaged initial k-space of the 2-D+t study.
+* ``rsvd``     — the paper's own nullspace route: randomized SVD of H(x)
+  for the r principal right singular vectors V, then r Householder
+  reflections for the basis Q orthogonal to V.
 * Circular axes: the lifting and everything built on it take ``wrap``
   flags for the circular convolution along time of the 2-D+t study.
 
@@ -35,10 +38,13 @@ from .descent import objective_grad, line_search, descent_step, solve, objective
 from .metrics import ser, rel_err
 from .pointwise import grad_at_points, residual_at_points, gram_entries
 from .init import time_average_init
+from .rsvd import (sketch_size, sketch_matrix, rsvd_right, householder_complement,
+                   nullspace_rsvd)
 
 __all__ = [
     "valid_extent", "hankel_matrix", "hankel_adjoint", "forward", "adjoint", "gram",
     "nullspace", "philox4x32_10", "philox_normals", "jl_matrix", "objective_grad",
     "line_search", "descent_step", "solve", "objective", "ser", "rel_err",
     "grad_at_points", "residual_at_points", "gram_entries", "time_average_init",
+    "sketch_size", "sketch_matrix", "rsvd_right", "householder_complement", "nullspace_rsvd",
 ]

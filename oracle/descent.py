@@ -27,6 +27,7 @@ import numpy as np
 from .hankel import hankel_matrix, hankel_adjoint
 from .nullspace import gram, nullspace
 from .jl import jl_matrix
+from .rsvd import nullspace_rsvd
 
 
 def _as_c128(a):
@@ -65,8 +66,12 @@ def descent_step(y, mask, F, kdims, lo, hi, wrap=None):
     return _as_c128(y) - eta * g, J, gn2, eta
 
 
-def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, start_outer=0, trace=None, wrap=None):
-    """Algorithm 1 with the Gram-eigendecomposition nullspace route.
+def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, start_outer=0, trace=None, wrap=None,
+          route="gram", ell=None):
+    """Algorithm 1.  ``route`` picks the nullspace update: "gram" (SVD of the
+    Gram matrix, DISCUSSION) or "rsvd" (randomized SVD and Householder
+    completion, THEORY; sketch of ``ell`` columns, default ceil(3r/2), drawn
+    for outer index i as ``rsvd.sketch_matrix(seed, i, ...)``).
 
     ``schedule``: list of (lo, hi, steps) per outer iteration.  ``p == 0``
     uses the whole nullspace (F = Q); otherwise F = Q P^(i,j) with the JL
@@ -78,13 +83,20 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, start_outer=0, trace=Non
     x = _as_c128(x0).copy()
     for i in range(start_outer, len(schedule)):
         lo, hi, steps = schedule[i]
-        Q, evals, _ = nullspace(gram(x, kdims, lo, hi, wrap), rank)
+        if route == "gram":
+            Q, evals, _ = nullspace(gram(x, kdims, lo, hi, wrap), rank)
+            tail = float(evals[: Q.shape[1]].sum())
+        elif route == "rsvd":
+            Q, _ = nullspace_rsvd(x, kdims, lo, hi, rank, seed, i, ell=ell, wrap=wrap)
+            tail = float("nan")
+        else:
+            raise ValueError("route must be 'gram' or 'rsvd'")
         y = x
         for j in range(steps):
             F = Q if p == 0 else Q @ jl_matrix(seed, i, j, Q.shape[1], p)
             y, J, gn2, eta = descent_step(y, mask, F, kdims, lo, hi, wrap)
             if trace is not None:
                 trace.append(dict(i=i, j=j, J=J, gnorm2=gn2, eta=eta,
-                                  tail=float(evals[: Q.shape[1]].sum())))
+                                  tail=tail))
         x = y
     return x
