@@ -2,13 +2,17 @@
 // Jacobi on the device (nullspace update of Algorithm 1, Gram route of the
 // DISCUSSION section).
 //
-// The matrix is split into 16-wide index blocks; a sweep visits every pair of
-// blocks once (round-robin "circle" schedule, nb - 1 rounds of nb/2 disjoint
-// pairs).  In each round one workgroup per pair diagonalises its 32 x 32
-// Hermitian subproblem with cyclic complex Jacobi rotations in LDS, and a
-// second kernel applies the block-diagonal unitary W to the whole matrix and
-// to the eigenvector accumulator (A <- W' A W, V <- V W) one 32 x 32 block per
-// workgroup, in place.  Pairs that are already diagonal are skipped, so
+// The matrix is split into 16-wide index blocks.  A sweep opens with one
+// round over the block pairs (2j, 2j + 1) that rotates every index pair of
+// each 32 x 32 subproblem (so every in-block pair is visited), then visits
+// every pair of blocks once (round-robin "circle" schedule, nb - 1 rounds of
+// nb/2 disjoint pairs) rotating only the 256 index pairs across the two
+// blocks (16 inner rounds instead of 31): each index pair is rotated once
+// per sweep.  In each round one workgroup per pair works on its subproblem
+// with complex Jacobi rotations in LDS, and a second kernel applies the
+// block-diagonal unitary W to the whole matrix and to the eigenvector
+// accumulator (A <- W' A W, V <- V W) one 32 x 32 block per workgroup, in
+// place.  Pairs that are already diagonal are skipped, so
 // warm-started solves (the previous eigenvectors as V0) cost little.  A sweep
 // ends with a relative off-diagonal test; FP64 throughout.
 #include <algorithm>
@@ -66,8 +70,10 @@ __device__ __forceinline__ void rot2x2(const Rot& ra, const Rot& rb, double2& b0
   b11 = cadd(csc(rb.sn, t10), csc(rb.cs, cmul(t11, eb)));
 }
 
+// Index blocks of pair `pair` in round r of the circle schedule; r < 0 is
+// the sweep's opening round, which pairs blocks 2 pair and 2 pair + 1.
 __device__ __forceinline__ void block_indices(int r, int nb, int pair, int* idx) {
-  const int P = circle_pos(pair, r, nb), Q = circle_pos(nb - 1 - pair, r, nb);
+  const int P = r < 0 ? 2 * pair : circle_pos(pair, r, nb), Q = r < 0 ? 2 * pair + 1 : circle_pos(nb - 1 - pair, r, nb);
   for (int i = 0; i < BS; ++i) {
     idx[i] = P * BS + i;
     idx[BS + i] = Q * BS + i;
@@ -123,6 +129,7 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   __shared__ int idx[SB];
   __shared__ int nrot_round, nrot_sweep[MAX_INNER];
   const int tid = threadIdx.x;
+  const bool cross = round >= 0;
   if (tid == 0) block_indices(round, nb, blockIdx.x, idx);
   if (tid < MAX_INNER) nrot_sweep[tid] = 0;
   __syncthreads();
@@ -138,7 +145,8 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
     const int i = tid >> 5, j = tid & 31;
     const double2 v = S[0][i][j];
     const double v2 = v.x * v.x + v.y * v.y;
-    const bool big = i != j && v2 > fl * fl && v2 > tol * tol * fabs(S[0][i][i].x * S[0][j][j].x);
+    const bool active = cross ? ((i < BS) != (j < BS)) : i != j;
+    const bool big = active && v2 > fl * fl && v2 > tol * tol * fabs(S[0][i][i].x * S[0][j][j].x);
     if (tid == 0) nrot_round = 0;
     __syncthreads();
     if (big) nrot_round = 1;
@@ -157,10 +165,14 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   const int ut = tid - 256, ui = ut >> 4, ub = ut & 15;
   int cur = 0, total = 0;
   for (int sweep = 0; sweep < MAX_INNER; ++sweep) {
-    for (int r = 0; r < SB - 1; ++r) {
+    for (int r = 0; r < (cross ? BS : SB - 1); ++r) {
       __syncthreads();
       if (tid < SB / 2) {
-        const int p = circle_pos(tid, r, SB), q = circle_pos(SB - 1 - tid, r, SB);
+        // opening round: every pair of the 32 indices (circle schedule);
+        // later rounds: only the pairs across the two blocks, whose
+        // in-block pairs the opening round has rotated
+        const int p = cross ? tid : circle_pos(tid, r, SB);
+        const int q = cross ? BS + (tid + r) % BS : circle_pos(SB - 1 - tid, r, SB);
         Rot ro;
         const bool did = make_rot_fast(S[cur][p][p].x, S[cur][q][q].x, S[cur][p][q], tol, fl, &ro);
         ro.p = p;
@@ -487,6 +499,11 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   double sums[2] = {0.0, 0.0}, prev = INFINITY;
   int32_t status = HICU_OK;
   for (;;) {
+    // opening round: blocks (2 j, 2 j + 1) with all their index pairs
+    hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)A, np, nb, -1, tol_inner,
+                       (const double*)dfloor, Ub, ident);
+    hipLaunchKernelGGL(apply_kernel, dim3(npair, npair), dim3(1024), 0, st, A, V, n, np, nb, -1, (const double2*)Ub,
+                       (const int*)ident, (double*)nullptr);
     for (int r = 0; r < nb - 1; ++r) {
       const bool last = r == nb - 2;
       hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)A, np, nb, r, tol_inner,
