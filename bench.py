@@ -190,6 +190,21 @@ def bench_gradient_steps(args, hicu, torch, np, synth, nested=False):
     t_eig = time.perf_counter() - t0
     del G
     _progress("gram %.3f s, nullspace %.3f s (%d sweeps)" % (t_gram, t_eig, sweeps))
+    # the paper's route for the same update: randomized SVD + Householder
+    t_rsvd = rsvd_dist = None
+    if not getattr(args, "no_routes", False) and n <= 2048:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Qr = hicu.nullspace_rsvd(x0, kd, r, seed=P.get("seed", 0), outer=0, lo=lo, hi=hi)
+        torch.cuda.synchronize()
+        t_rsvd = time.perf_counter() - t0
+        # largest principal angle between the two nullspaces (sine)
+        Qh, Qrh = Q.cpu().numpy().astype(np.complex128), Qr.cpu().numpy().astype(np.complex128)
+        sig = np.linalg.svd(Qh.conj().T @ Qrh, compute_uv=False)
+        rsvd_dist = float(np.sqrt(max(0.0, 1.0 - float(sig.min()) ** 2)))
+        del Qr
+        torch.cuda.empty_cache()
+        _progress("rsvd nullspace %.3f s (sin of largest angle to the Gram route's %.3g)" % (t_rsvd, rsvd_dist))
     p = Q.shape[1]
     precs = [q.strip() for q in args.paths.split(",") if q.strip()]
     if nested:
@@ -235,7 +250,9 @@ def bench_gradient_steps(args, hicu, torch, np, synth, nested=False):
                             filter_group=hicu.filter_group(x0.shape, kd, p, best, lo, hi)[0],
                             compact_residual=hicu.filter_group(x0.shape, kd, p, best, lo, hi)[1], path=best),
                 pts_filters_per_s=round(b["iters_per_s"] * s_out * p, 1),
-                setup=dict(gram_s=round(t_gram, 3), nullspace_s=round(t_eig, 3), eig_sweeps=int(sweeps)),
+                setup=dict(gram_s=round(t_gram, 3), nullspace_s=round(t_eig, 3), eig_sweeps=int(sweeps),
+                           rsvd_s=None if t_rsvd is None else round(t_rsvd, 3),
+                           rsvd_sketch=min(n, (3 * r + 1) // 2), rsvd_sin_angle_to_gram=rsvd_dist),
                 paths={k: dict(iters_per_s=round(v["iters_per_s"], 4), ms_per_step=round(v["ms_per_step"], 3),
                                steps=v["steps"], J=v["J"], kernel_ms={kk: round(vv["total_ms"] / v["steps"], 3)
                                                                       for kk, vv in v["prof"].items()})
@@ -448,6 +465,7 @@ def main():
                     help="comma list of fp32, bf16x3, bf16+refine, fp16+refine (volumes: fp32, bf16, fp16)")
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-routes", action="store_true", help="skip the rSVD-route solve of the 2-D workloads")
     ap.add_argument("--no-volume", action="store_true",
                     help="skip the nested 256 x 320 x 320 x 8 volume gradient-step record")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -522,10 +540,11 @@ def main():
 
     wrap = P.get("wrap")
 
-    def run(prec, refine):
+    def run(prec, refine, route="gram"):
         # the 2-D+t study starts from the time-averaged k-space (part of the timed work)
         xs = hicu.time_average_init(x0, mask, axis=0) if P.get("init") == "time_average" else x0
-        return hicu.solve(xs, mask, kd, r, sched, p=P["p"], seed=P["seed"], prec=prec, refine_steps=refine, wrap=wrap)
+        return hicu.solve(xs, mask, kd, r, sched, p=P["p"], seed=P["seed"], prec=prec, refine_steps=refine, wrap=wrap,
+                          route=route)
 
     if args.autotune:
         from paper_2004_08962_amd import batch as hb
@@ -551,6 +570,36 @@ def main():
         results[path] = dict(prec=prec, refine=refine, seconds=dt, ms_per_step=1e3 * dt / args.steps,
                              iters_per_s=args.steps * total_iters / dt, ser=ser(x), prof=prof, x=x.cpu().numpy(),
                              final_J=trace[-1]["J"], sweeps=[t["sweeps"] for t in trace[::sched[0][2]]])
+
+    # Nullspace routes (DISCUSSION: rSVD against the SVD of the Gram): the
+    # fastest path again with the randomized SVD + Householder update.
+    routes = None
+    if not args.no_routes and n <= 2048:
+        rpath = "bf16+refine" if "bf16+refine" in results else next(iter(results))
+        rv = results[rpath]
+        for _ in range(args.warmup):
+            run(rv["prec"], rv["refine"], "rsvd")
+        torch.cuda.synchronize()
+        hicu.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            xr, _ = run(rv["prec"], rv["refine"], "rsvd")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rprof = hicu.profile_end()
+        _progress("%s, rsvd route: %.1f ms per solve" % (rpath, 1e3 * dt / args.steps))
+
+        def null_ms(prof, keys):
+            return round(sum(prof[k]["total_ms"] for k in keys if k in prof) / args.steps, 3)
+
+        routes = dict(path=rpath, sketch=min(n, (3 * r + 1) // 2),
+                      gram=dict(ms_per_step=round(rv["ms_per_step"], 3), iters_per_s=round(rv["iters_per_s"], 3),
+                                ser_db=round(rv["ser"], 5), nullspace_ms=null_ms(rv["prof"], ("gram", "eig"))),
+                      rsvd=dict(ms_per_step=round(1e3 * dt / args.steps, 3),
+                                iters_per_s=round(args.steps * total_iters / dt, 3), ser_db=round(ser(xr), 5),
+                                d_ser_vs_gram=round(ser(xr) - rv["ser"], 5), nullspace_ms=null_ms(rprof, ("rsvd",)),
+                                kernel_ms={kk: round(vv["total_ms"] / args.steps, 3) for kk, vv in rprof.items()}))
+        del xr
 
     # fixed SER: anchored on the FP64 oracle's reconstruction (on the FP32
     # path when the oracle leg is skipped)
@@ -585,6 +634,8 @@ def main():
                                ser_db=None if anchor is None else round(anchor, 5), tol_db=0.1,
                                d_ser_vs_oracle=None if oracle_ser is None else round(b["ser"] - oracle_ser, 5)),
                 roofline=roofline)
+    if routes is not None:
+        line["nullspace_routes"] = routes
     if cb is not None:
         line["cpu_baseline"] = cb
     if not args.no_volume and args.workload == "2d_256x232x16":

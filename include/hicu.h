@@ -168,6 +168,49 @@ int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G_dev, const void* V
                        void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Nullspace basis by randomized SVD and Householder completion (THEORY:
+ * first numerical technique; Algorithm 1, rSVD and Householder steps; cost
+ * model).  The paper's own route: H_S(x) and its adjoint are applied to a
+ * sketch, and neither the Hankel matrix nor its Gram is formed.
+ *   1. Omega^(outer): n x l complex Gaussian test matrix (as hicu_sketch);
+ *   2. Y = H_S(x) Omega by the FP32 forward contraction (s x l kept whole);
+ *   3. W = H_S(x)' Y and M = Y'Y in one FP64 pass over the region
+ *      (fixed-order sums, so the result is deterministic);
+ *   4. V = the `rank` principal right singular vectors of B = U' H_S(x) with
+ *      U an orthonormal basis of range(Y), from the eigendecompositions of M
+ *      and of B B' (eigendirections of M below 1e-10 of its largest, the
+ *      rounding floor of the FP32 sketch, are dropped);
+ *   5. Q = the trailing n - rank columns of H_1 ... H_r, the Householder
+ *      reflections of V's QR: H_j = I - 2 w w' with w the unit vector along
+ *      a - alpha e_j, a the j-th column of the partly reduced V from row j
+ *      down, alpha = -exp(i arg a_0) ||a|| (exp(i arg 0) = 1).
+ * ell        sketch columns l with rank <= l <= n; 0 = ceil(3 rank / 2)
+ *            capped at n (the paper's 3r/2 applications of H and H').
+ * seed, outer, stream_id  counter words of the sketch draw.
+ * Q_dev      complex64 n x (n - rank), row-major (no phase rule: the
+ *            reflections fix the basis).
+ * sv_dev     optional double[l]: singular values of B, largest first.
+ * sweeps_host optional: Jacobi sweeps of the eigensolve of B B'.
+ * Memory: the s x l complex64 sketch Y dominates (the paper's 1.5 r s).
+ * rank = 0 writes the identity.  Kernel masks and circular axes are
+ * supported; n above 2048 returns HICU_ERR_UNSUPPORTED.  Synchronous on
+ * `stream`.  Returns HICU_ERR_NOCONV if the eigensolve of B B' hit its
+ * sweep limit (outputs are still written).
+ * ------------------------------------------------------------------------ */
+size_t hicu_nullspace_rsvd_workspace_bytes(const hicu_geom* geom, int32_t rank, int32_t ell);
+int32_t hicu_nullspace_rsvd(const hicu_geom* geom, const void* x_dev, int32_t rank, int32_t ell, uint64_t seed,
+                            uint32_t outer, uint32_t stream_id, void* Q_dev, double* sv_dev, int32_t* sweeps_host,
+                            void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The sketch Omega alone: complex64 n x ell row-major; element e has real
+ * part z[2e] and imaginary part z[2e + 1], z the unit normals of the Philox
+ * stream (seed, outer, 2^32 - 1, stream_id) mapped as in hicu_jl_compress
+ * (no 1/sqrt(p) scale).  The inner word 2^32 - 1 is never a gradient-step
+ * index, so no JL draw repeats a sketch draw. */
+int32_t hicu_sketch(int32_t n, int32_t ell, uint64_t seed, uint32_t outer, uint32_t stream_id, void* Om_dev,
+                    void* stream);
+
+/* ------------------------------------------------------------------------
  * JL compression F = Q P   (THEORY: second numerical technique; Algorithm 1,
  * JL step).  P is real (nq x p), i.i.d. N(0, 1/p), drawn on the device from
  * Philox4x32-10 with key (seed lo, seed hi) and counter
@@ -275,7 +318,8 @@ int32_t hicu_update(const hicu_geom* geom, void* x_dev, const void* g_dev,
                     const double* eta_dev, void* stream);
 
 /* ------------------------------------------------------------------------
- * Full reconstruction, Algorithm 1 (Gram-eigendecomposition nullspace route).
+ * Full reconstruction, Algorithm 1 (nullspace by the Gram eigendecomposition or
+ * by randomized SVD, see hicu_params.route).
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t rank;             /* r: 0 <= r < n */
@@ -288,7 +332,11 @@ typedef struct {
   uint64_t seed;            /* JL seed */
   int32_t prec;             /* hicu_prec of the contractions */
   int32_t refine_steps;     /* the last refine_steps gradient steps of the run use HICU_FP32 */
-  int32_t warm_start;       /* 1: start each eigensolve from the previous eigenvectors */
+  int32_t warm_start;       /* 1: start each eigensolve from the previous eigenvectors (route 0) */
+  int32_t route;            /* nullspace update: 0 = eigendecomposition of the Gram (DISCUSSION),
+                               1 = randomized SVD + Householder (THEORY), as hicu_nullspace_rsvd
+                               with the sketch of outer iteration i drawn for (seed, i, stream 0) */
+  int32_t sketch;           /* route 1: sketch columns l (0 = ceil(3 rank / 2)) */
 } hicu_params;
 
 /* One record per gradient step, filled when trace_host != NULL

@@ -29,7 +29,8 @@ class Geom(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("rank", c_int32), ("p", c_int32), ("n_outer", c_int32), ("start_outer", c_int32),
                 ("steps", ctypes.POINTER(c_int32)), ("regions", ctypes.POINTER(c_int64)),
-                ("seed", c_uint64), ("prec", c_int32), ("refine_steps", c_int32), ("warm_start", c_int32)]
+                ("seed", c_uint64), ("prec", c_int32), ("refine_steps", c_int32), ("warm_start", c_int32),
+                ("route", c_int32), ("sketch", c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -66,6 +67,11 @@ SIGNATURES = {
     "hicu_nullspace_workspace_bytes": (c_size_t, [c_int32]),
     "hicu_nullspace": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  ctypes.POINTER(c_int32), c_void_p, c_size_t, c_void_p]),
+    "hicu_nullspace_rsvd_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),
+    "hicu_nullspace_rsvd": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_int32, c_int32, c_uint64, c_uint32,
+                                      c_uint32, c_void_p, c_void_p, ctypes.POINTER(c_int32), c_void_p, c_size_t,
+                                      c_void_p]),
+    "hicu_sketch": (c_int32, [c_int32, c_int32, c_uint64, c_uint32, c_uint32, c_void_p, c_void_p]),
     "hicu_jl_compress": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_uint64, c_uint32, c_uint32,
                                    c_uint32, c_void_p, c_void_p, c_void_p]),
     "hicu_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),

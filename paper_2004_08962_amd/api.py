@@ -146,6 +146,42 @@ def nullspace(G, rank, V0=None, want_V=True):
     return Q, ev, V, int(sweeps.value)
 
 
+def nullspace_rsvd(x, kdims, rank, ell=0, seed=0, outer=0, stream_id=0, lo=None, hi=None, wrap=None,
+                   want_sv=False):
+    """Q (complex64 (n, n - rank)) by randomized SVD of H_S(x) and Householder
+    completion; with want_sv also the sketched B's singular values
+    (float64 (l,), largest first) and the Jacobi sweeps.  ``ell`` = 0 takes
+    ceil(3 rank / 2) sketch columns."""
+    _shape_checks(x.shape)
+    lib = load()
+    _dev(x, torch.complex64, "x")
+    g = geom(x.shape, kdims, lo, hi, wrap)
+    n = int(lib.hicu_num_taps(ctypes.byref(g)))
+    check(n, "hicu_num_taps")
+    if not 0 <= int(rank) < n:
+        raise ValueError("rank %d outside [0, %d)" % (int(rank), n))
+    wsb = int(lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), int(rank), int(ell)))
+    if wsb == 0:
+        raise ValueError("invalid rSVD arguments (sketch size %d, rank %d, n %d)" % (int(ell), int(rank), n))
+    ws = _workspace(wsb, x.device)
+    l = int(ell) if ell else min(n, (3 * int(rank) + 1) // 2)
+    Q = torch.empty((n, n - int(rank)), dtype=torch.complex64, device=x.device)
+    sv = torch.empty((max(l, 1),), dtype=torch.float64, device=x.device) if want_sv else None
+    sweeps = ctypes.c_int32(0)
+    check(lib.hicu_nullspace_rsvd(ctypes.byref(g), _ptr(x), int(rank), int(ell), int(seed), int(outer),
+                                  int(stream_id), _ptr(Q), _ptr(sv), ctypes.byref(sweeps), _ptr(ws), wsb,
+                                  _stream()), "hicu_nullspace_rsvd")
+    return (Q, sv[:l] if int(rank) > 0 else sv[:0], int(sweeps.value)) if want_sv else Q
+
+
+def sketch(n, ell, seed, outer, stream_id=0, device="cuda"):
+    """The rSVD test matrix Omega (complex64 (n, ell)) drawn on the device."""
+    Om = torch.empty((int(n), int(ell)), dtype=torch.complex64, device=device)
+    check(load().hicu_sketch(int(n), int(ell), int(seed), int(outer), int(stream_id), _ptr(Om), _stream()),
+          "hicu_sketch")
+    return Om
+
+
 def jl_compress(Q, p, seed, outer, inner, stream_id=0, return_P=False):
     """F = Q P with P drawn on the device (Philox4x32-10 + Box-Muller)."""
     if Q.dim() != 2:
@@ -234,9 +270,21 @@ def update(x, gv, eta, kdims=(1, 1, 1)):
     return x
 
 
+_ROUTES = {"gram": 0, "rsvd": 1}
+
+
+def _route(route):
+    if route not in _ROUTES:
+        raise ValueError("route must be 'gram' or 'rsvd', got %r" % (route,))
+    return _ROUTES[route]
+
+
 def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_steps=0, warm_start=True,
-          start_outer=0, out=None, ws=None, raise_nonfinite=True, wrap=None):
+          start_outer=0, out=None, ws=None, raise_nonfinite=True, wrap=None, route="gram", ell=0):
     """Algorithm 1 on the device.  ``schedule``: list of (lo, hi, steps).
+    ``route``: nullspace update by the Gram eigendecomposition ("gram") or by
+    randomized SVD + Householder ("rsvd", ``ell`` sketch columns, 0 =
+    ceil(3 rank / 2)).
     Returns (x, trace) with trace a list of dicts (one per gradient step).
     ``ws``: optional uint8 CUDA workspace of at least solve_workspace_bytes()
     bytes (allocated here otherwise).  With raise_nonfinite=False a run that
@@ -262,6 +310,8 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     prm.prec = _prec(prec)
     prm.refine_steps = int(refine_steps)
     prm.warm_start = 1 if warm_start else 0
+    prm.route = _route(route)
+    prm.sketch = int(ell)
     total = sum(int(s[2]) for s in schedule[start_outer:])
     tr = (Trace * max(1, total))()
     x = torch.empty_like(x0) if out is None else out
@@ -280,7 +330,8 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     return x, trace
 
 
-def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0, wrap=None):
+def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0, wrap=None,
+                          route="gram", ell=0):
     """Device bytes hicu_solve needs for this problem and schedule."""
     g = geom(shape, kdims, wrap=wrap)
     n_outer = len(schedule)
@@ -292,6 +343,7 @@ def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine
     prm.steps = ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32))
     prm.regions = ctypes.cast(regs, ctypes.POINTER(ctypes.c_int64))
     prm.prec, prm.refine_steps = _prec(prec), int(refine_steps)
+    prm.route, prm.sketch = _route(route), int(ell)
     return int(load().hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm)))
 
 

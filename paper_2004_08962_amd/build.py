@@ -11,7 +11,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhicu.so")
 SOURCES = ["conv.hip", "conv_f32.hip", "conv_bf16.hip", "conv_bf16x3.hip", "conv_f16.hip", "gram.hip", "eig.hip",
-           "ops.hip", "prof.cpp", "step.cpp", "tune.cpp", "batch.hip", "api.cpp", "noalloc.hip"]
+           "ops.hip", "prof.cpp", "step.cpp", "tune.cpp", "batch.hip", "api.cpp", "noalloc.hip",
+           "rsvd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,

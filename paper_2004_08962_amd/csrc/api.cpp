@@ -1,6 +1,6 @@
 // C ABI of the HICU hot-path library: argument validation, workspace
 // planning and launch sequencing.  Every arithmetic step runs in the HIP
-// kernels of conv.hip, gram.hip, eig.hip and ops.hip.
+// kernels of conv.hip, gram.hip, eig.hip, rsvd.hip and ops.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +14,7 @@
 #include "gram.h"
 #include "ops.h"
 #include "prof.h"
+#include "rsvd.h"
 #include "step.h"
 
 namespace hicu {
@@ -145,6 +146,35 @@ int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G, const void* V0, v
   return run_eig(n, rank, G, V0, Q, evals, V, sweeps, ws, ws_bytes, (hipStream_t)stream, false);
 }
 
+size_t hicu_nullspace_rsvd_workspace_bytes(const hicu_geom* gm, int32_t rank, int32_t ell) {
+  Geo g;
+  if (make_geo(gm, &g) != HICU_OK || rank < 0 || rank >= g.n || g.n > kRsvdMaxN) return 0;
+  if (rank == 0) return 256;
+  const int l = ell == 0 ? default_sketch(rank, g.n) : ell;
+  if (l < rank || l > g.n) return 0;
+  return rsvd_workspace(g, rank, l);
+}
+
+int32_t hicu_nullspace_rsvd(const hicu_geom* gm, const void* x, int32_t rank, int32_t ell, uint64_t seed,
+                            uint32_t outer, uint32_t sid, void* Q, double* sv, int32_t* sweeps, void* ws,
+                            size_t ws_bytes, void* stream) {
+  Geo g;
+  HICU_TRY(make_geo(gm, &g));
+  if (!x || !Q) return HICU_ERR_ARG;
+  if (rank < 0 || rank >= g.n) return HICU_ERR_RANK;
+  if (g.n > kRsvdMaxN) return HICU_ERR_UNSUPPORTED;
+  const int l = ell == 0 ? default_sketch(rank, g.n) : ell;
+  if (rank > 0 && (l < rank || l > g.n)) return HICU_ERR_ARG;
+  ProfScope ps("rsvd", (hipStream_t)stream);
+  return run_rsvd(g, x, rank, l, seed, outer, sid, reinterpret_cast<float2*>(Q), sv, sweeps, ws, ws_bytes,
+                  (hipStream_t)stream);
+}
+
+int32_t hicu_sketch(int32_t n, int32_t ell, uint64_t seed, uint32_t outer, uint32_t sid, void* Om, void* stream) {
+  if (n < 1 || ell < 1 || !Om) return HICU_ERR_ARG;
+  return launch_sketch(n, ell, seed, outer, sid, reinterpret_cast<float2*>(Om), (hipStream_t)stream);
+}
+
 int32_t hicu_jl_compress(int32_t n, int32_t nq, int32_t p, const void* Q, uint64_t seed, uint32_t outer,
                          uint32_t inner, uint32_t sid, void* F, double* P, void* stream) {
   if (n < 1 || nq < 1 || p < 1 || !Q || !F) return HICU_ERR_ARG;
@@ -225,8 +255,9 @@ struct SolvePlan {
   std::vector<Geo> geos;
   int64_t total_steps = 0;
   int n = 0, nq = 0, pf = 0;
-  size_t ws_step = 0, ws_gram = 0;
-  size_t o_g, o_G, o_V0, o_V1, o_Q, o_F, o_sc, o_cnt, o_eig, o_gram, o_step, total;
+  int ell = 0;
+  size_t ws_step = 0, ws_gram = 0, ws_rsvd = 0;
+  size_t o_g, o_G, o_V0, o_V1, o_Q, o_F, o_sc, o_cnt, o_eig, o_gram, o_rsvd, o_step, total;
 };
 
 int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* sp) {
@@ -238,6 +269,13 @@ int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* 
   const int n = full.n, r = prm->rank;
   if (r < 0 || r >= n) return HICU_ERR_RANK;
   if (prm->p < 0) return HICU_ERR_RANK;
+  if (prm->route != 0 && prm->route != 1) return HICU_ERR_ARG;
+  const bool rsvd = prm->route == 1;
+  if (rsvd) {
+    if (n > kRsvdMaxN) return HICU_ERR_UNSUPPORTED;
+    sp->ell = prm->sketch == 0 ? default_sketch(r, n) : prm->sketch;
+    if (r > 0 && (sp->ell < r || sp->ell > n)) return HICU_ERR_ARG;
+  }
   sp->n = n;
   sp->nq = n - r;
   sp->pf = prm->p == 0 ? sp->nq : prm->p;
@@ -255,25 +293,35 @@ int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* 
     if (prm->steps[i] < 0) return HICU_ERR_ARG;
     if (i >= prm->start_outer) sp->total_steps += prm->steps[i];
   }
-  sp->ws_step = sp->ws_gram = 0;
+  sp->ws_step = sp->ws_gram = sp->ws_rsvd = 0;
   for (int i = prm->start_outer; i < prm->n_outer; ++i) {
     const size_t a = step_workspace(sp->geos[i], sp->pf, prm->prec), b = step_workspace(sp->geos[i], sp->pf, P_F32);
     if (a == 0 || b == 0) return HICU_ERR_UNSUPPORTED;
     sp->ws_step = std::max(sp->ws_step, std::max(a, b));
-    sp->ws_gram = std::max(sp->ws_gram, gram_workspace(sp->geos[i]));
+    if (rsvd) {
+      const size_t w = r == 0 ? 256 : rsvd_workspace(sp->geos[i], r, sp->ell);
+      if (w == 0) return HICU_ERR_UNSUPPORTED;
+      sp->ws_rsvd = std::max(sp->ws_rsvd, w);
+    } else {
+      sp->ws_gram = std::max(sp->ws_gram, gram_workspace(sp->geos[i]));
+    }
   }
+  // The Gram route keeps G, two eigenvector sets (warm start) and the
+  // eigensolver's workspace; the rSVD route only its own workspace.
   const size_t N = (size_t)full.npts * full.nc;
+  const size_t nn = rsvd ? 0 : (size_t)n * n * sizeof(double2);
   size_t off = 0;
   sp->o_g = off; off += al(N * sizeof(float2));
-  sp->o_G = off; off += al((size_t)n * n * sizeof(double2));
-  sp->o_V0 = off; off += al((size_t)n * n * sizeof(double2));
-  sp->o_V1 = off; off += al((size_t)n * n * sizeof(double2));
+  sp->o_G = off; off += al(nn);
+  sp->o_V0 = off; off += al(nn);
+  sp->o_V1 = off; off += al(nn);
   sp->o_Q = off; off += al((size_t)n * sp->nq * sizeof(float2));
   sp->o_F = off; off += al((size_t)n * sp->pf * sizeof(float2));
   sp->o_sc = off; off += al((size_t)std::max<int64_t>(1, sp->total_steps) * 3 * sizeof(double));
   sp->o_cnt = off; off += al(sizeof(unsigned long long));
-  sp->o_eig = off; off += al(eig_workspace(n));
+  sp->o_eig = off; off += al(rsvd ? 0 : eig_workspace(n));
   sp->o_gram = off; off += al(sp->ws_gram);
+  sp->o_rsvd = off; off += al(sp->ws_rsvd);
   sp->o_step = off; off += al(sp->ws_step);
   sp->total = off;
   return HICU_OK;
@@ -322,21 +370,25 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
   std::vector<double> hs(3 * (size_t)std::max<int64_t>(1, total_steps));
   for (int i = prm->start_outer; i < prm->n_outer && status != HICU_ERR_NONFINITE; ++i) {
     const Geo& gi = pl.geos[i];
-    {
-      ProfScope ps("gram", st, 4.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);
-      HICU_TRY(launch_gram(gi, x, at(ws, pl.o_G), at(ws, pl.o_gram), pl.ws_gram, st));
-    }
     int32_t sw = 0;
     int32_t es;
-    {
+    if (prm->route == 1) {
+      ProfScope ps("rsvd", st);
+      es = run_rsvd(gi, x, r, pl.ell, prm->seed, (uint32_t)i, 0u, reinterpret_cast<float2*>(at(ws, pl.o_Q)),
+                    nullptr, &sw, at(ws, pl.o_rsvd), pl.ws_rsvd, st);
+    } else {
+      {
+        ProfScope ps("gram", st, 4.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);
+        HICU_TRY(launch_gram(gi, x, at(ws, pl.o_G), at(ws, pl.o_gram), pl.ws_gram, st));
+      }
       ProfScope ps("eig", st);
       es = run_eig(n, r, at(ws, pl.o_G), (prm->warm_start && have_prev) ? Vprev : nullptr, at(ws, pl.o_Q), nullptr,
                    Vcur, &sw, at(ws, pl.o_eig), eig_workspace(n), st, prm->p == 0);
+      std::swap(Vprev, Vcur);
+      have_prev = true;
     }
     if (es < 0 && es != HICU_ERR_NOCONV) return es;
     if (es == HICU_ERR_NOCONV) status = HICU_ERR_NOCONV;
-    std::swap(Vprev, Vcur);
-    have_prev = true;
     const int64_t step0 = step;
     int prepped_prec = -1;  // precision whose weights of this iteration's F are in the workspace
     for (int j = 0; j < prm->steps[i]; ++j, ++step) {

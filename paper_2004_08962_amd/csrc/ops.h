@@ -6,6 +6,8 @@ namespace hicu {
 
 int32_t launch_jl(const float2* Q, int n, int nq, int p, uint64_t seed, uint32_t outer, uint32_t inner,
                   uint32_t sid, float2* F, double* Pout, hipStream_t st);
+// Randomized-SVD sketch Omega (n x l complex64) for (seed, outer, sid).
+int32_t launch_sketch(int n, int ell, uint64_t seed, uint32_t outer, uint32_t sid, float2* Om, hipStream_t st);
 int32_t launch_eta(const double* part, int64_t count, const double* gnorm2, double* eta, hipStream_t st);
 int32_t launch_update(float2* x, const float2* g, const double* eta, int64_t count, hipStream_t st);
 int32_t launch_zero(void* ptr, size_t bytes, hipStream_t st);

@@ -77,6 +77,27 @@ int32_t launch_jl(const float2* Q, int n, int nq, int p, uint64_t seed, uint32_t
   return HICU_OK;
 }
 
+// Sketch of the randomized SVD: Omega (n x l complex64, row-major); element
+// e takes normals 2e (real part) and 2e + 1 (imaginary part) of the stream
+// (seed, outer, 2^32 - 1, sid) -- the inner counter word 2^32 - 1 is never a
+// gradient-step index, so the sketch shares no draw with the JL matrices.
+__global__ __launch_bounds__(256) void sketch_kernel(int64_t count, uint64_t seed, uint32_t outer, uint32_t sid,
+                                                     float2* Om) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const double re = philox_normal(2 * e, seed, outer, 0xFFFFFFFFu, sid);
+  const double im = philox_normal(2 * e + 1, seed, outer, 0xFFFFFFFFu, sid);
+  Om[e] = make_float2((float)re, (float)im);
+}
+
+int32_t launch_sketch(int n, int ell, uint64_t seed, uint32_t outer, uint32_t sid, float2* Om, hipStream_t st) {
+  const int64_t count = (int64_t)n * ell;
+  if (count <= 0) return HICU_OK;
+  hipLaunchKernelGGL(sketch_kernel, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, count, seed, outer, sid, Om);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
 // eta = gnorm2 / (2 sum(part)), 0 when the sum is 0 or anything is non-finite.
 __global__ __launch_bounds__(1024) void eta_kernel(const double* part, int64_t count, const double* gnorm2,
                                                    double* eta) {

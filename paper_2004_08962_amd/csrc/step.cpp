@@ -377,6 +377,43 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
   return HICU_OK;
 }
 
+// Y = H_S(x) F kept whole (s x p complex64, point-major, filter fastest):
+// the sketch of the randomized SVD.  One forward launch over all p filters.
+size_t forward_store_workspace(const Geo& g, int p, int prec) {
+  if (g.kmasked) {
+    const size_t inner = forward_store_workspace(box_geo(g), p, prec);
+    return inner ? kmask_head(g, p) + inner : 0;
+  }
+  StepPlan sp;
+  if (make_step_plan(g, p, prec, false, &sp) != HICU_OK) return 0;
+  return sp.total;
+}
+
+int32_t forward_store_impl(const Geo& g, const void* x, const void* F, int p, int prec, void* Y, void* ws,
+                           size_t ws_bytes, hipStream_t st) {
+  if (prec == P_F16) return HICU_ERR_UNSUPPORTED;
+  if (g.kmasked) {
+    const size_t h = kmask_head(g, p);
+    if (!ws || ws_bytes < h) return HICU_ERR_WORKSPACE;
+    HICU_TRY(launch_kmask_scatter(g, reinterpret_cast<const float2*>(F), p, reinterpret_cast<float2*>(ws), st));
+    return forward_store_impl(box_geo(g), x, ws, p, prec, Y, at(ws, h), ws_bytes - h, st);
+  }
+  StepPlan sp;
+  HICU_TRY(make_step_plan(g, p, prec, false, &sp));
+  if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
+  {
+    ProfScope ps("prep_weights", st);
+    HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
+                                 at(ws, sp.off_Bflo), st));
+  }
+  fill_forward_args(g, x, sp, ws, reinterpret_cast<float*>(Y), reinterpret_cast<double*>(at(ws, sp.off_pf)));
+  ConvPlan cf = sp.cf;
+  cf.gy = group_col_blocks(cf, p);
+  ProfScope ps(conv_tag(0, prec), st, 8.0 * g.n * (double)p * (double)g.s,
+               8.0 * (double)region_points(g) * g.nc + 8.0 * (double)g.s * p);
+  return launch_conv(cf, st);
+}
+
 size_t step_workspace(const Geo& g, int p, int prec) {
   if (g.kmasked) {
     const size_t inner = step_workspace(box_geo(g), p, prec);

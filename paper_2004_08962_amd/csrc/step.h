@@ -65,5 +65,10 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
 int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const void* F, int p, int prec,
                          double* eta, void* ws, size_t ws_bytes, hipStream_t st, bool grad_weights = false);
 size_t step_workspace(const Geo& g, int p, int prec);
+// Y = H_S(x) F stored whole as s x p complex64 (point-major, filter fastest),
+// for any precision but FP16.
+size_t forward_store_workspace(const Geo& g, int p, int prec);
+int32_t forward_store_impl(const Geo& g, const void* x, const void* F, int p, int prec, void* Y, void* ws,
+                           size_t ws_bytes, hipStream_t st);
 
 }  // namespace hicu

@@ -129,6 +129,42 @@ def test_solve_workspace_is_the_callers(lib):
     assert lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(badp)) == 0
 
 
+def test_rsvd_workspace_and_validation(lib):
+    """The rSVD route sizes its workspace from the sketch Y (s x l complex64)
+    and refuses bad sketch sizes, ranks and tap counts before any launch."""
+    g = _geom(dims=(1, 256, 232), nc=16)
+    s, n = 252 * 228, 400
+    b = lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 120, 0)
+    assert b >= s * 180 * 8 + 2 * n * 180 * 16     # Y (l = 180), W and B'
+    assert b < s * 180 * 8 + (256 << 20)
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 120, 200) > b
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 120, 119) == 0   # l < r
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 120, 401) == 0   # l > n
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 400, 0) == 0     # r >= n
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g), 0, 0) > 0
+    big = _geom(dims=(1, 64, 64), nc=100, k=(1, 5, 5))                               # n = 2500
+    assert lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(big), 10, 0) == 0
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.hicu_nullspace_rsvd(ctypes.byref(g), fake, 400, 0, 1, 0, 0, fake, None, None, fake, b, None) == -3
+    assert lib.hicu_nullspace_rsvd(ctypes.byref(g), fake, 120, 100, 1, 0, 0, fake, None, None, fake, b, None) == -1
+    assert lib.hicu_nullspace_rsvd(ctypes.byref(g), None, 120, 0, 1, 0, 0, fake, None, None, fake, b, None) == -1
+    assert lib.hicu_nullspace_rsvd(ctypes.byref(big), fake, 10, 0, 1, 0, 0, fake, None, None, fake, b, None) == -7
+    assert lib.hicu_sketch(0, 5, 1, 0, 0, fake, None) == -1
+    # hicu_solve with the rSVD route keeps no Gram, eigenvectors or n x n eigensolver workspace
+    g2 = _geom()
+    prm, keep = _params(rank=30)
+    gram_b = lib.hicu_solve_workspace_bytes(ctypes.byref(g2), ctypes.byref(prm))
+    prm.route, prm.sketch = 1, 0
+    rsvd_b = lib.hicu_solve_workspace_bytes(ctypes.byref(g2), ctypes.byref(prm))
+    assert rsvd_b > 0
+    assert rsvd_b >= lib.hicu_nullspace_rsvd_workspace_bytes(ctypes.byref(g2), 30, 0)
+    prm.sketch = 29
+    assert lib.hicu_solve_workspace_bytes(ctypes.byref(g2), ctypes.byref(prm)) == 0
+    prm.route, prm.sketch = 2, 0
+    assert lib.hicu_solve_workspace_bytes(ctypes.byref(g2), ctypes.byref(prm)) == 0
+    assert gram_b > 0
+
+
 def test_circular_axis_validation(lib):
     """A circular axis must span the whole array, and wrap bits must name
     given axes; both are refused before any launch."""
