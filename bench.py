@@ -282,6 +282,16 @@ def bench_batch(args, hicu, torch, np, synth):
         items.append(dict(x0=x0, x=x0.clone(), mask=torch.from_numpy(P["mask"]).cuda(), Q=Q, p=P["p"],
                           kdims=P["kdims"], lo=(0, 0, 0), hi=tuple(P["x0"].shape[:3]), seed=P["seed"]))
     torch.cuda.synchronize()
+    # batched shapes from the autotuner, timed on the slice with the most work
+    big = max(range(count), key=lambda i: hicu.num_taps(items[i]["x0"].shape, items[i]["kdims"]) * items[i]["p"]
+              * int(np.prod([d - k + 1 for d, k in zip(probs[i]["x0"].shape[:3], probs[i]["kdims"])])))
+    tuned = {}
+    if not args.no_batch_tune:
+        Fb = items[big]["Q"][:, :items[big]["p"]].contiguous()
+        for prec in [q.strip() for q in args.paths.split(",") if q.strip()]:
+            tuned[prec] = hb.autotune(items[big]["x0"], Fb, items[big]["kdims"], prec=prec, batched=True)
+        del Fb
+        _progress("batched shapes tuned on slice %d: %s" % (big, tuned))
     s_total = sum(int(np.prod([d - k + 1 for d, k in zip(P["x0"].shape[:3], P["kdims"])])) for P in probs)
     pf_total = sum(int(np.prod([d - k + 1 for d, k in zip(P["x0"].shape[:3], P["kdims"])])) * P["p"] for P in probs)
     results = {}
@@ -317,21 +327,34 @@ def bench_batch(args, hicu, torch, np, synth):
     d = conv[dom]
     achieved = d["flops"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[best]
+    # The slices' contractions have p = Nc filters: 8 n p s flops against
+    # at least (Nc + p) 8 bytes per point, an intensity below the BF16 ridge
+    # (2.5 PF / 8 TB/s), so the bound is HBM when flops / peak < bytes / bandwidth.
+    gbs = d["bytes"] / d["launches"] / (d["avg_ms"] * 1e-3) / 1e9
+    t_mfma = d["flops"] / d["launches"] / (peak * 1e12)
+    t_hbm = d["bytes"] / d["launches"] / (HBM_PEAK_GBS * 1e9)
+    if t_hbm > t_mfma:
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                    mfma_tflops=round(achieved, 3), mfma_frac=round(achieved / peak, 4))
+    else:
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s", frac=round(achieved / peak, 4),
+                    hbm_gbs=round(gbs, 1))
+    roof.update(traffic=None, kernel=dom, avg_ms=round(d["avg_ms"], 4), launches=d["launches"],
+                flops_per_launch=d["flops"] / d["launches"], bytes_per_launch=d["bytes"] / d["launches"],
+                intensity_flop_per_byte=round(d["flops"] / max(d["bytes"], 1.0), 1))
     line = dict(metric=METRIC, value=round(r["iters_per_s"], 2), unit="slice gradient iters/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(r["ms_per_step"], 4),
                 higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype=DTYPE[best], data="synthetic",
                 config=dict(workload=args.workload, slices=count, valid_outputs=s_total,
                             step="one gradient iteration of every slice, graph replay", path=best,
-                            tiles=dict(fwd=r["info"]["fwd_tile"], adj=r["info"]["adj_tile"])),
+                            tiles=dict(fwd=r["info"]["fwd_tile"], adj=r["info"]["adj_tile"]),
+                            tuned_on_slice=None if not tuned else big, tuned=tuned or None),
                 pts_filters_per_s=round(pf_total * args.steps / r["seconds"], 1),
                 paths={k: dict(iters_per_s=round(v["iters_per_s"], 2), ms_per_step=round(v["ms_per_step"], 4),
                                kernel_ms={kk: round(vv["total_ms"] / args.steps, 4) for kk, vv in v["prof"].items()})
                        for k, v in results.items()},
-                roofline=dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                              frac=round(achieved / peak, 4), traffic=None, kernel=dom,
-                              avg_ms=round(d["avg_ms"], 4), launches=d["launches"],
-                              flops_per_launch=d["flops"] / d["launches"]))
+                roofline=roof)
     print(json.dumps(line), flush=True)
 
 
@@ -466,6 +489,7 @@ def main():
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-routes", action="store_true", help="skip the rSVD-route solve of the 2-D workloads")
+    ap.add_argument("--no-batch-tune", action="store_true", help="batched workload: keep the fixed shape rule")
     ap.add_argument("--no-volume", action="store_true",
                     help="skip the nested 256 x 320 x 320 x 8 volume gradient-step record")
     ap.add_argument("--calibrate-copy", action="store_true",

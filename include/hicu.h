@@ -433,20 +433,30 @@ void hicu_batch_destroy(hicu_batch* batch);
  * HIP events and stores the fastest in a process-wide cache that every later
  * plan with the same (contraction, precision, kernel box, coils, filters,
  * size class) uses.  choice (optional, int32[4]): forward shape id and
- * channel chunk, adjoint shape id and channel chunk.  Synchronous.  hicu_tune_save / hicu_tune_load
- * write / read the cache as text (load returns the number of entries read
- * or a negative status); hicu_tune_clear empties it.
+ * channel chunk, adjoint shape id and channel chunk.  Synchronous.  Shapes
+ * are timed on one filter group of the gradient (all p filters when Y = H(x)F
+ * fits the filter-group budget), so the workspace never exceeds a step's.
+ * hicu_autotune_batched does the same over the shapes that have persistent
+ * batched kernels and stores the result for the batched runtime:
+ * hicu_batch_create takes the batched choice stored for the class of its
+ * largest problem (most n p s), else its fixed rule.  Neither tunes FP16
+ * for the batch (the batched path runs no FP16).  hicu_tune_save /
+ * hicu_tune_load write / read the cache as text (load returns the number
+ * of entries read or a negative status); hicu_tune_clear empties it.
  * ------------------------------------------------------------------------ */
 size_t hicu_autotune_workspace_bytes(const hicu_geom* geom, int32_t p, int32_t prec);
 int32_t hicu_autotune(const hicu_geom* geom, const void* x_dev, const void* F_dev, int32_t p, int32_t prec,
                       void* ws_dev, size_t ws_bytes, int32_t* choice, void* stream);
+int32_t hicu_autotune_batched(const hicu_geom* geom, const void* x_dev, const void* F_dev, int32_t p,
+                              int32_t prec, void* ws_dev, size_t ws_bytes, int32_t* choice, void* stream);
 int32_t hicu_tune_save(const char* path);
 int32_t hicu_tune_load(const char* path);
 int32_t hicu_tune_clear(void);
 /* Pin the tile shape of one contraction (role 0 forward/line search, role 1
- * adjoint; tile = shape id < hicu_tile_count(), a packing shape (D > 1)
- * only for role 1; chunk_c = adjoint channel chunk) for problems of this
- * geometry, filter count and precision. */
+ * adjoint; roles 2 and 3 the same for the batched runtime, shapes with
+ * batched kernels only; tile = shape id < hicu_tile_count(), a packing
+ * shape (D > 1) only for role 1; chunk_c = adjoint channel chunk) for
+ * problems of this geometry, filter count and precision. */
 int32_t hicu_tune_put(const hicu_geom* geom, int32_t p, int32_t prec, int32_t role, int32_t tile,
                       int32_t chunk_c);
 

@@ -101,6 +101,8 @@ SIGNATURES = {
     "hicu_autotune_workspace_bytes": (c_size_t, [ctypes.POINTER(Geom), c_int32, c_int32]),
     "hicu_autotune": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_size_t,
                                 ctypes.POINTER(c_int32), c_void_p]),
+    "hicu_autotune_batched": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_int32, c_int32, c_void_p,
+                                        c_size_t, ctypes.POINTER(c_int32), c_void_p]),
     "hicu_tune_save": (c_int32, [ctypes.c_char_p]),
     "hicu_tune_load": (c_int32, [ctypes.c_char_p]),
     "hicu_tune_clear": (c_int32, []),

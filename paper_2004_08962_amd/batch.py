@@ -78,9 +78,11 @@ class Batch:
             pass
 
 
-def autotune(x, F, kdims, lo=None, hi=None, prec="fp32"):
+def autotune(x, F, kdims, lo=None, hi=None, prec="fp32", batched=False):
     """Time every tile shape on this problem; returns the chosen
-    (forward shape id, forward chunk, adjoint shape id, adjoint chunk)."""
+    (forward shape id, forward chunk, adjoint shape id, adjoint chunk).
+    batched=True times the shapes that have batched kernels and stores the
+    choice for Batch objects whose largest problem is of this class."""
     lib = load()
     _dev(x, torch.complex64, "x")
     _dev(F, torch.complex64, "F")
@@ -89,8 +91,9 @@ def autotune(x, F, kdims, lo=None, hi=None, prec="fp32"):
     wsb = lib.hicu_autotune_workspace_bytes(ctypes.byref(g), p, _prec(prec))
     ws = _workspace(wsb, x.device)
     choice = (ctypes.c_int32 * 4)()
-    check(lib.hicu_autotune(ctypes.byref(g), _ptr(x), _ptr(F), p, _prec(prec), _ptr(ws), ws.numel(), choice,
-                            _stream()), "hicu_autotune")
+    fn = lib.hicu_autotune_batched if batched else lib.hicu_autotune
+    check(fn(ctypes.byref(g), _ptr(x), _ptr(F), p, _prec(prec), _ptr(ws), ws.numel(), choice, _stream()),
+          "hicu_autotune_batched" if batched else "hicu_autotune")
     return tuple(choice)
 
 

@@ -11,6 +11,7 @@
 #include "ops.h"
 #include "prof.h"
 #include "step.h"
+#include "tune.h"
 
 namespace hicu {
 namespace {
@@ -167,6 +168,8 @@ struct hicu_batch_s {
   int max_p = 0, max_nq = 0;
   bool any_zero = false, any_jl = false;
   double flops = 0.0;  // algorithmic flops of one contraction over all problems (8 n p s each)
+  // algorithmic HBM bytes of the forward, adjoint and line-search launches
+  double bytes_f = 0.0, bytes_a = 0.0, bytes_z = 0.0;
   // workspace layout of the shared tables
   size_t off_tables = 0, off_counter = 0, total_bytes = 0;
   size_t t_conv_f = 0, t_conv_a = 0, t_conv_z = 0, t_start_f = 0, t_start_a = 0, t_prep_f = 0, t_prep_a = 0,
@@ -209,16 +212,45 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     fa = std::max<int>(fa, (int)cdiv(2 * P.g.nc, 16));
     any3d = any3d || P.g.k[0] > 1;
   }
-  // batched shapes: ids 0-2 (1 x 16 x 8) and 13-15 (2 x 16 x 4) with FN = 1, 2, 4
+  // Shapes: the autotuner's batched choice (hicu_autotune_batched) for the
+  // class of the problem with the most work, when it has one; else the
+  // widest column block any problem needs among the batched shapes 0-2
+  // (1 x 16 x 8) and 13-15 (2 x 16 x 4) with FN = 1, 2, 4.
   auto pick = [&](int frags) {
     const int fn = frags >= 3 ? 2 : frags - 1;
     return any3d ? 13 + fn : fn;
   };
   b->tf = pick(ff);
   b->ta = pick(fa);
+  int chunk_a = 0;  // adjoint channel chunk from the tuner (0: first that plans of 16, 8, 4)
+  {
+    int big = 0;
+    double wmax = -1.0;
+    for (int q = 0; q < count; ++q) {
+      const double w = (double)b->probs[q].g.n * b->probs[q].p * (double)b->probs[q].g.s;
+      if (w > wmax) {
+        wmax = w;
+        big = q;
+      }
+    }
+    TuneEntry e;
+    const Geo& gb = b->probs[big].g;
+    if (tune_lookup(kRoleBatchForward, prec, gb, b->probs[big].p, &e) && tile_batch_ok(e.tile) &&
+        tile_D(e.tile) == 1 && (tile_cfg(e.tile).T0 == 1 || any3d))
+      b->tf = e.tile;
+    if (tune_lookup(kRoleBatchAdjoint, prec, gb, b->probs[big].p, &e) && tile_batch_ok(e.tile) &&
+        tile_D(e.tile) == 1 && (tile_cfg(e.tile).T0 == 1 || any3d)) {
+      b->ta = e.tile;
+      chunk_a = e.chunk_c;
+    }
+  }
   size_t off = 0;
+  // Register-pipelined staging pays only when a launch streams several
+  // channel chunks; with one chunk per tile (up to 16 coils or filters) the
+  // plain staging skips its per-slot index set-up.
   b->pipe_f = true;
   b->pipe_a = true;
+  bool multi_f = false, multi_a = false;
   for (int q = 0; q < count; ++q) {
     BatchProblem& P = b->probs[q];
     const Geo& g = P.g;
@@ -229,15 +261,19 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     const int64_t oe[3] = {g.hi[0] - g.lo[0], g.hi[1] - g.lo[1], g.hi[2] - g.lo[2]};
     s = HICU_ERR_UNSUPPORTED;
     for (int cc : {16, 8, 4}) {
-      sp.wa = weight_shape(prec, g.k, P.p, std::min(cc, P.p), 2 * g.nc, 1);
+      const int c = chunk_a > 0 ? chunk_a : cc;
+      sp.wa = weight_shape(prec, g.k, P.p, std::min(c, P.p), 2 * g.nc, 1);
       s = plan_conv(prec, b->ta, g.k, sp.wa, sp.wa.nchunks, oe, 2 * g.nc, &sp.ca);
       if (s != HICU_ERR_UNSUPPORTED) break;
+      chunk_a = 0;  // the tuned chunk does not plan for this problem: fall back
     }
     if (s != HICU_OK) return s;
     sp.nf_blocks = sp.cf.gx * sp.cf.gy;
     sp.na_blocks = sp.ca.gx * sp.ca.gy;
     b->pipe_f = b->pipe_f && conv_can_pipe(sp.cf);
     b->pipe_a = b->pipe_a && conv_can_pipe(sp.ca);
+    multi_f = multi_f || sp.cf.a.nchunks > 1;
+    multi_a = multi_a || sp.ca.a.nchunks > 1;
     b->lds_f = std::max(b->lds_f, sp.cf.lds_bytes);
     b->lds_a = std::max(b->lds_a, sp.ca.lds_bytes);
     b->total_f += sp.nf_blocks;
@@ -252,6 +288,10 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     b->any_zero = b->any_zero || !full_region(g);
     b->any_jl = b->any_jl || P.jl;
     b->flops += 8.0 * g.n * (double)P.p * (double)g.s;
+    const double nS = (double)region_points(g), ys = 8.0 * (double)g.s * P.p;
+    b->bytes_f += 8.0 * nS * g.nc + ys;
+    b->bytes_a += ys + nS + 8.0 * nS * g.nc;
+    b->bytes_z += 8.0 * nS * g.nc;
     const size_t es = esize(prec), parts = prec == P_BF16X3 ? 2 : 1;
     P.off_Y = take(&off, (size_t)g.s * P.p * sizeof(float2));
     P.off_Bf = take(&off, sp.wf.elems * es);
@@ -264,6 +304,8 @@ int32_t batch_plan(const hicu_batch_item* items, int count, int prec, hicu_batch
     P.off_g = take(&off, (size_t)N * sizeof(float2));
     P.off_F = take(&off, P.jl ? (size_t)g.n * P.p * sizeof(float2) : 0);
   }
+  b->pipe_f = b->pipe_f && multi_f;
+  b->pipe_a = b->pipe_a && multi_a;
   if ((size_t)b->max_nq * sizeof(double) > 65536) return HICU_ERR_UNSUPPORTED;
   b->off_tables = off;
   b->t_conv_f = take(&off, count * sizeof(ConvArgs));
@@ -379,7 +421,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
                     reinterpret_cast<const int64_t*>(at(ws, b->t_start_f)), count, b->total_f,
                     (unsigned)std::min<int64_t>(grid, b->total_f), b->lds_f};
   {
-    ProfScope ps("batch_conv_fwd", st, b->flops);
+    ProfScope ps("batch_conv_fwd", st, b->flops, b->bytes_f);
     HICU_TRY(launch_conv_batch(f, st));
   }
   hipLaunchKernelGGL(reduce_batch_kernel, dim3(count), dim3(1024), 0, st,
@@ -393,7 +435,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
                     reinterpret_cast<const int64_t*>(at(ws, b->t_start_a)), count, b->total_a,
                     (unsigned)std::min<int64_t>(grid, b->total_a), b->lds_a};
   {
-    ProfScope ps("batch_conv_adj", st, b->flops);
+    ProfScope ps("batch_conv_adj", st, b->flops, b->bytes_a);
     HICU_TRY(launch_conv_batch(a, st));
   }
   hipLaunchKernelGGL(reduce_batch_kernel, dim3(count), dim3(1024), 0, st,
@@ -401,7 +443,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
   BatchConvLaunch z = f;
   z.args = reinterpret_cast<const ConvArgs*>(at(ws, b->t_conv_z));
   {
-    ProfScope ps("batch_conv_els", st, b->flops);
+    ProfScope ps("batch_conv_els", st, b->flops, b->bytes_z);
     HICU_TRY(launch_conv_batch(z, st));
   }
   hipLaunchKernelGGL(eta_batch_kernel, dim3(count), dim3(1024), 0, st,

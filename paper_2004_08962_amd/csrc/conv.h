@@ -80,13 +80,13 @@ struct TileCfg {
   X(0, 1, 8, 1, 1, 1, 1, 1)      \
   X(1, 1, 8, 1, 2, 1, 1, 1)      \
   X(2, 1, 8, 1, 4, 1, 1, 1)      \
-  X(3, 1, 4, 1, 1, 1, 1, 0)      \
-  X(4, 1, 4, 1, 2, 1, 1, 0)      \
-  X(5, 1, 4, 1, 4, 1, 1, 0)      \
+  X(3, 1, 4, 1, 1, 1, 1, 1)      \
+  X(4, 1, 4, 1, 2, 1, 1, 1)      \
+  X(5, 1, 4, 1, 4, 1, 1, 1)      \
   X(6, 1, 8, 2, 2, 1, 0, 0)      \
   X(7, 1, 8, 2, 4, 1, 0, 0)      \
   X(8, 1, 16, 2, 4, 1, 0, 0)     \
-  X(9, 1, 16, 1, 2, 1, 1, 0)     \
+  X(9, 1, 16, 1, 2, 1, 1, 1)     \
   X(10, 1, 8, 1, 4, 2, 1, 0)     \
   X(11, 1, 16, 1, 4, 2, 1, 0)    \
   X(12, 1, 8, 1, 4, 4, 1, 0)     \
@@ -123,6 +123,8 @@ constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 // Complex values per thread of the register-pipelined chunk staging.
 constexpr int kStageSlots = 16;
 TileCfg tile_cfg(int id);
+// Whether the shape has a persistent batched kernel.
+bool tile_batch_ok(int id);
 // Block columns of a shape.
 inline int block_cols(const TileCfg& t) { return 16 * t.WC * t.FN; }
 

@@ -100,6 +100,15 @@ TileCfg tile_cfg(int id) {
   return (id >= 0 && id < kNumTiles) ? table[id] : TileCfg{0, 0, 0, 0, 0};
 }
 
+bool tile_batch_ok(int id) {
+  static const bool table[kNumTiles] = {
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) B != 0,
+      HICU_TILES(HICU_TILE_ROW)
+#undef HICU_TILE_ROW
+  };
+  return id >= 0 && id < kNumTiles && table[id];
+}
+
 static bool tile_pipe_ok(int id) {
   static const bool table[kNumTiles] = {
 #define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) P != 0,

@@ -16,6 +16,8 @@ struct TuneEntry {
 
 // role 0: forward / line-search contraction (input = k-space, output = filters)
 // role 1: adjoint contraction (input = residual, output = coils)
+// roles 2, 3: the same for the batched runtime (shapes with batched kernels)
+constexpr int kRoleBatchForward = 2, kRoleBatchAdjoint = 3;
 bool tune_lookup(int role, int prec, const Geo& g, int p, TuneEntry* e);
 void tune_store(int role, int prec, const Geo& g, int p, const TuneEntry& e);
 

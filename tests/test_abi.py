@@ -165,6 +165,23 @@ def test_rsvd_workspace_and_validation(lib):
     assert gram_b > 0
 
 
+def test_tuner_workspace_and_batched_roles(lib):
+    """The tuner times one filter group, so its workspace stays within a
+    gradient step's even for the full volume; batched roles 2/3 accept only
+    shapes with batched kernels."""
+    g = _geom(dims=(256, 320, 320), nc=8, k=(5, 5, 5))
+    tune = lib.hicu_autotune_workspace_bytes(ctypes.byref(g), 900, 1)
+    step = lib.hicu_workspace_bytes(ctypes.byref(g), 900, 1)
+    assert 0 < tune <= 2 * step
+    assert tune < 20e9      # one 64-filter group of Y, not the 181 GB of all 900
+    g2 = _geom()
+    assert lib.hicu_tune_put(ctypes.byref(g2), 70, 1, 2, 7, 16) == -1    # shape 7 has no batched kernel
+    assert lib.hicu_tune_put(ctypes.byref(g2), 70, 1, 2, 4, 16) == 0
+    assert lib.hicu_tune_put(ctypes.byref(g2), 70, 1, 3, 10, 16) == -1   # packing shape, no batched kernel
+    assert lib.hicu_tune_put(ctypes.byref(g2), 70, 1, 4, 4, 16) == -1    # no such role
+    assert lib.hicu_tune_clear() == 0
+
+
 def test_circular_axis_validation(lib):
     """A circular axis must span the whole array, and wrap bits must name
     given axes; both are refused before any launch."""

@@ -144,3 +144,61 @@ def test_autotune_and_cache(env, tmp_path):
     hb.tune_clear()
     assert hb.tune_load(path) == 2
     hb.tune_clear()
+
+
+def test_batched_autotune_drives_the_batch(env):
+    """hicu_autotune_batched on the problem with the most work: the batch
+    then runs the tuned shapes (batched kernels only) and still equals the
+    single-problem steps on those shapes."""
+    hicu, hb, torch, probs = env
+    hb.tune_clear()
+    big = max(range(len(probs)), key=lambda i: hicu.num_taps(probs[i]["x0"].shape, probs[i]["kd"]) * probs[i]["p"]
+              * int(np.prod([h - l - k + 1 for l, h, k in zip(probs[i]["lo"], probs[i]["hi"], probs[i]["kd"])])))
+    P = probs[big]
+    F = P["Q"][:, :P["p"]]
+    choice = hb.autotune(_dev(torch, P["x0"]), _dev(torch, np.ascontiguousarray(F)), P["kd"], P["lo"], P["hi"],
+                         prec="bf16", batched=True)
+    print("batched choice", choice, flush=True)
+    batched_tiles = {0, 1, 2, 3, 4, 5, 9, 13, 14, 15}
+    assert choice[0] in batched_tiles and choice[2] in batched_tiles
+    b, items = _make_batch(hb, torch, probs, "bf16")
+    info = b.info()
+    assert (info["fwd_tile"], info["adj_tile"]) == (choice[0], choice[2])
+    b.close()
+    # the single-problem cache (roles 0/1) is untouched by the batched tuning
+    hb.tune_clear()
+    with pytest.raises(Exception):
+        hb.tune_put(P["x0"].shape, P["kd"], P["p"], "bf16", 2, 7, 16, P["lo"], P["hi"])  # no batched kernel
+    hb.tune_put(P["x0"].shape, P["kd"], P["p"], "bf16", 2, 4, 16, P["lo"], P["hi"])
+    hb.tune_clear()
+
+
+def test_autotune_under_filter_groups(env):
+    """With a tiny residual budget the gradient runs in filter groups; the
+    tuner times one group (its workspace holds one group's Y) and the tuned
+    plans keep the oracle's rounding bounds."""
+    hicu, hb, torch, probs = env
+    P = synth.make_problem("2d_64x64x4")
+    x = P["x0"].astype(np.complex64)
+    kd, lo, hi = P["kdims"], (0, 0, 0), (1, 64, 64)
+    Q, _, _ = oracle.nullspace(oracle.gram(x.astype(np.complex128), kd, lo, hi), P["rank"])
+    F = np.ascontiguousarray(Q.astype(np.complex64))
+    p = F.shape[1]
+    s = 60 * 60
+    try:
+        hicu.set_filter_group_budget(s * 64 * 8)     # groups of 64 filters
+        assert hicu.filter_group(x.shape, kd, p)[0] == 64
+        hb.tune_clear()
+        choice = hb.autotune(_dev(torch, x), _dev(torch, F), kd, lo, hi, prec="bf16")
+        J, g, gn2 = hicu.objective_grad(_dev(torch, x), _dev(torch, P["mask"]), _dev(torch, F), kd, lo, hi,
+                                        prec="bf16")
+    finally:
+        hicu.set_filter_group_budget(0)
+        hb.tune_clear()
+    assert 0 <= choice[0] < hb.tile_count() and 0 <= choice[2] < hb.tile_count()
+    xr, Fr = x.astype(np.complex128), F.astype(np.complex128)
+    Jr, gr, _ = oracle.objective_grad(xr, P["mask"], Fr, kd, lo, hi)
+    Y, eY = forward_bound(xr, Fr, kd, lo, hi, "bf16")
+    assert abs(J.item() - Jr) <= sumsq_bound(Y, eY)
+    eg = grad_bound(xr, P["mask"], Fr, kd, lo, hi, "bf16", groups=2)
+    assert np.all(np.abs(g.cpu().numpy() - gr) <= eg + 1e-30)
