@@ -167,7 +167,7 @@ int32_t hicu_nullspace_rsvd(const hicu_geom* gm, const void* x, int32_t rank, in
   if (rank > 0 && (l < rank || l > g.n)) return HICU_ERR_ARG;
   ProfScope ps("rsvd", (hipStream_t)stream);
   return run_rsvd(g, x, rank, l, seed, outer, sid, reinterpret_cast<float2*>(Q), sv, sweeps, ws, ws_bytes,
-                  (hipStream_t)stream);
+                  (hipStream_t)stream, true);
 }
 
 int32_t hicu_sketch(int32_t n, int32_t ell, uint64_t seed, uint32_t outer, uint32_t sid, void* Om, void* stream) {
@@ -375,7 +375,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
     if (prm->route == 1) {
       ProfScope ps("rsvd", st);
       es = run_rsvd(gi, x, r, pl.ell, prm->seed, (uint32_t)i, 0u, reinterpret_cast<float2*>(at(ws, pl.o_Q)),
-                    nullptr, &sw, at(ws, pl.o_rsvd), pl.ws_rsvd, st);
+                    nullptr, &sw, at(ws, pl.o_rsvd), pl.ws_rsvd, st, prm->p > 0);
     } else {
       {
         ProfScope ps("gram", st, 4.0 * (double)gi.s * n * n, 8.0 * region_points(gi) * gi.nc);

@@ -361,6 +361,9 @@ int32_t batch_bind(hicu_batch_s* b, void* ws, hipStream_t st) {
                       reinterpret_cast<double*>(at(ws, P.off_pa)), sp.ca.a);
     ca[q] = sp.ca.a;
     ca[q].vec = conv_vec(ca[q]);
+    // pipelined staging moves four aligned channels per slot
+    if (cf[q].vec != 4 || cz[q].vec != 4) b->pipe_f = false;
+    if (ca[q].vec != 4) b->pipe_a = false;
     sf[q + 1] = sf[q] + sp.nf_blocks;
     sa[q + 1] = sa[q] + sp.na_blocks;
     pf[q] = make_prep_args(0, prec, g, F, P.p, sp.wf, at(ws, P.off_Bf), at(ws, P.off_Bflo));

@@ -316,9 +316,10 @@ int32_t launch_conv(const ConvPlan& p, hipStream_t st) {
     if (a.yb == 2 && a.accumulate) return HICU_ERR_UNSUPPORTED;
     if (a.yb != 1 && a.yb != 2) return HICU_ERR_ARG;
   }
-  const bool pipe = a.yb == 0 && a.nchunks > 1 && conv_can_pipe(p);
   ConvPlan q = p;
   q.a.vec = conv_vec(a);
+  // pipelined staging moves four aligned channels per slot
+  const bool pipe = a.yb == 0 && a.nchunks > 1 && conv_can_pipe(p) && q.a.vec == 4;
   int32_t s;
   if (p.prec == P_F16) s = launch_prec_impl<P_F16>(q, pipe, st);
   else if (p.prec == P_F32) s = launch_prec_impl<P_F32>(q, pipe, st);

@@ -347,7 +347,6 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
 
   const int half_ps = a.ps >> 1;
   const int npts_halo = a.h[0] * a.h[1] * a.h[2];
-  const int nstage = npts_halo * half_ps;
   const int nkb = a.nkb, nk1 = a.k[1];
   const int total = a.k[0] * nk1 * nkb;
 
@@ -525,65 +524,69 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
       compute_chunk(chg);
     }
   } else {
-    // Slot i of this thread stages complex value e = tid + 256 i of the
-    // chunk: its point's input offset (or -1 outside the validity box), its
-    // LDS offset and its channel slot, computed once for all chunks.
-    int64_t goff[kStageSlots];
-    int loff[kStageSlots], csl[kStageSlots];
+    // Slot i of this thread stages the group of VS = 4 consecutive channels
+    // g = tid + 256 i of the chunk (pipelined launches require the input's
+    // channel runs to be 16-byte aligned, a.vec == 4): its point's input
+    // offset (or -1 outside the validity box), its LDS offset and its first
+    // channel, computed once for all chunks.  Four channels per slot cut the
+    // per-value index work and the slot registers by four.
+    {
+      constexpr int VS = 4;
+      constexpr int NSL = kStageSlots / VS;
+      const int gper = half_ps / VS;  // channel groups per staged point (padding included)
+      const int nst = npts_halo * gper;
+      int64_t goff[NSL];
+      int loff[NSL], csl[NSL];
 #pragma unroll
-    for (int i = 0; i < kStageSlots; ++i) {
-      const int e = tid + 256 * i;
-      goff[i] = -2;
-      loff[i] = 0;
-      csl[i] = 0;
-      if (e < nstage) {
-        const int cs = e % half_ps;
-        const int pt = e / half_ps;
-        const int hh2 = pt % a.h[2];
-        const int q = pt / a.h[2];
-        const int hh1 = q % a.h[1];
-        const int hh0 = q / a.h[1];
-        const int64_t i0 = wrap_index(a.org[0] + base0 + hh0, a.wp[0]);
-        const int64_t i1 = wrap_index(a.org[1] + base1 + hh1, a.wp[1]);
-        const int64_t i2 = wrap_index(a.org[2] + base2 + hh2, a.wp[2]);
-        const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
-                        i2 < a.vhi[2];
-        goff[i] = ok ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] : -1;
-        loff[i] = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cs;
-        csl[i] = cs;
-      }
-    }
-    float2 buf[kStageSlots];
-    auto load = [&](const int chg) {
-      const int cbase = chg * a.chunk_c;
-#pragma unroll
-      for (int i = 0; i < kStageSlots; ++i) {
-        float2 v = make_float2(0.f, 0.f);
-        if (goff[i] >= 0 && csl[i] < a.chunk_c && cbase + csl[i] < a.cin)
-          v = a.in[goff[i] + (cbase - a.chan_base) + csl[i]];
-        buf[i] = v;
-      }
-    };
-    auto store = [&]() {
-#pragma unroll
-      for (int i = 0; i < kStageSlots; ++i)
-        if (goff[i] != -2) {
-          const float v[2] = {buf[i].x, buf[i].y};
-          stage_store<PREC, 1>(lds, lds_lo, loff[i], v, in_sc);
+      for (int i = 0; i < NSL; ++i) {
+        const int e = tid + 256 * i;
+        goff[i] = -2;
+        loff[i] = 0;
+        csl[i] = 0;
+        if (e < nst) {
+          const int cs = (e % gper) * VS;
+          const int pt = e / gper;
+          const int hh2 = pt % a.h[2];
+          const int q = pt / a.h[2];
+          const int hh1 = q % a.h[1];
+          const int hh0 = q / a.h[1];
+          const int64_t i0 = wrap_index(a.org[0] + base0 + hh0, a.wp[0]);
+          const int64_t i1 = wrap_index(a.org[1] + base1 + hh1, a.wp[1]);
+          const int64_t i2 = wrap_index(a.org[2] + base2 + hh2, a.wp[2]);
+          const bool ok = i0 >= a.vlo[0] && i0 < a.vhi[0] && i1 >= a.vlo[1] && i1 < a.vhi[1] && i2 >= a.vlo[2] &&
+                          i2 < a.vhi[2];
+          goff[i] = ok ? i0 * a.is[0] + i1 * a.is[1] + i2 * a.is[2] : -1;
+          loff[i] = (hh0 * a.h[1] + hh1) * a.rs + hh2 * a.ps + 2 * cs;
+          csl[i] = cs;
         }
-    };
-    load(a.ch0);
-    __syncthreads();  // row tails zeroed before the first chunk lands
-    store();
-    __syncthreads();
-    for (int ch = 0; ch < a.nchunks; ++ch) {
-      const bool more = ch + 1 < a.nchunks;
-      if (more) load(a.ch0 + ch + 1);
-      compute_chunk(a.ch0 + ch);
-      if (more) {
-        __syncthreads();
-        store();
-        __syncthreads();
+      }
+      float buf[NSL][2 * VS];
+      auto load = [&](const int chg) {
+        const int cbase = chg * a.chunk_c;
+#pragma unroll
+        for (int i = 0; i < NSL; ++i) {
+          const int nv = (goff[i] >= 0 && csl[i] < a.chunk_c) ? max(0, min(VS, a.cin - (cbase + csl[i]))) : 0;
+          load_unit<VS>(a.in, nv ? goff[i] + (cbase - a.chan_base) + csl[i] : 0, nv, buf[i]);
+        }
+      };
+      auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < NSL; ++i)
+          if (goff[i] != -2) stage_store<PREC, VS>(lds, lds_lo, loff[i], buf[i], in_sc);
+      };
+      load(a.ch0);
+      __syncthreads();  // row tails zeroed before the first chunk lands
+      store();
+      __syncthreads();
+      for (int ch = 0; ch < a.nchunks; ++ch) {
+        const bool more = ch + 1 < a.nchunks;
+        if (more) load(a.ch0 + ch + 1);
+        compute_chunk(a.ch0 + ch);
+        if (more) {
+          __syncthreads();
+          store();
+          __syncthreads();
+        }
       }
     }
   }

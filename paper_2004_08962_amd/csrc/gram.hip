@@ -355,33 +355,59 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
       for (int j = 0; j < T; ++j) acc[u][i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+  // Fast path (uniform per wave): when every shifted point of the cell box
+  // lies inside the region for each of the wave's shifts, no index wraps
+  // and no bound fails, so the shifted operand sits at a fixed offset from
+  // the unshifted one (the large core cell always qualifies).
+  bool fast = true;
+  int64_t doff[DW];
+#pragma unroll
+  for (int u = 0; u < DW; ++u) {
+    doff[u] = ((int64_t)d[u][0] * a.d1 * a.d2 + (int64_t)d[u][1] * a.d2 + d[u][2]) * two_nc;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      fast = fast && cst[ax] + d[u][ax] >= a.lo[ax] && cst[ax] + cln[ax] - 1 + d[u][ax] < a.hi[ax];
+  }
   int64_t q = q_begin + g;
   int64_t p2 = q % cln[2], p1 = (q / cln[2]) % cln[1], p0 = q / (cln[2] * cln[1]);
+  auto base_of = [&]() { return (((cst[0] + p0) * a.d1 + (cst[1] + p1)) * a.d2 + (cst[2] + p2)) * two_nc; };
+  int64_t base = base_of();
   auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
   auto fetch = [&](float (&av)[T], float (&bv)[DW][T]) {
     const bool ok = q < q_end;
-    const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
-    const int64_t base = ok ? ((w0 * a.d1 + w1) * a.d2 + w2) * two_nc : 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
+    if (fast) {
 #pragma unroll
-    for (int u = 0; u < DW; ++u) {
-      const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
-                    v2 = wrap_to(w2 + d[u][2], a.per[2]);
-      const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
-                       v2 >= a.lo[2] && v2 < a.hi[2];
-      const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+      for (int u = 0; u < DW; ++u)
 #pragma unroll
-      for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
+        for (int i = 0; i < T; ++i) bv[u][i] = (ok && hok[u] && okc[i]) ? a.x[base + doff[u] + 16 * i + m] : 0.f;
+    } else {
+      const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
+#pragma unroll
+      for (int u = 0; u < DW; ++u) {
+        const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
+                      v2 = wrap_to(w2 + d[u][2], a.per[2]);
+        const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
+                         v2 >= a.lo[2] && v2 < a.hi[2];
+        const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
+      }
     }
     q += 4;
     p2 += 4;
-    while (p2 >= cln[2]) {
-      p2 -= cln[2];
-      if (++p1 == cln[1]) {
-        p1 = 0;
-        ++p0;
+    if (p2 < cln[2]) {
+      base += 4 * two_nc;
+    } else {
+      while (p2 >= cln[2]) {
+        p2 -= cln[2];
+        if (++p1 == cln[1]) {
+          p1 = 0;
+          ++p0;
+        }
       }
+      base = base_of();
     }
   };
   constexpr int PF = kGramAhead;

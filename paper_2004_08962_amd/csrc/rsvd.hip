@@ -456,7 +456,7 @@ size_t rsvd_workspace(const Geo& g, int rank, int ell) {
 }
 
 int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, uint32_t outer, uint32_t sid,
-                 float2* Q, double* sv, int32_t* sweeps, void* ws, size_t ws_bytes, hipStream_t st) {
+                 float2* Q, double* sv, int32_t* sweeps, void* ws, size_t ws_bytes, hipStream_t st, bool basis) {
   const int n = g.n;
   if (n > kRsvdMaxN) return HICU_ERR_UNSUPPORTED;
   if (rank < 0 || rank >= n) return HICU_ERR_RANK;
@@ -536,7 +536,9 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
   int32_t sw = 0;
   {
     ProfScope ps("rsvd_eig", st);
-    const int32_t es = run_eig(ell, 0, M, nullptr, nullptr, evM, ZM, &sw, at(ws, L.eig), L.eig_bytes, st, false);
+    // any orthonormal basis of range(Y) serves, so M's eigenvectors need
+    // only the eigensolver's projector accuracy
+    const int32_t es = run_eig(ell, 0, M, nullptr, nullptr, evM, ZM, &sw, at(ws, L.eig), L.eig_bytes, st, true);
     if (es < 0 && es != HICU_ERR_NOCONV) return es;
   }
   hipLaunchKernelGGL(lowdin_kernel, dim3((unsigned)cdiv((int64_t)ell * ell, 256)), dim3(256), 0, st, ZM,
@@ -548,7 +550,7 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
   int32_t status = HICU_OK;
   {
     ProfScope ps("rsvd_eig", st);
-    const int32_t es = run_eig(ell, 0, C, nullptr, nullptr, evC, ZC, &sw, at(ws, L.eig), L.eig_bytes, st, false);
+    const int32_t es = run_eig(ell, 0, C, nullptr, nullptr, evC, ZC, &sw, at(ws, L.eig), L.eig_bytes, st, !basis);
     if (es < 0 && es != HICU_ERR_NOCONV) return es;
     if (es == HICU_ERR_NOCONV) status = es;
   }
