@@ -28,6 +28,7 @@
 // (2K-1)^D / 2 shifts x Nc^2 coil pairs x |S| points.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "gram.h"
 #include "step.h"
@@ -355,86 +356,113 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
       for (int j = 0; j < T; ++j) acc[u][i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  // Fast path (uniform per wave): when every shifted point of the cell box
-  // lies inside the region for each of the wave's shifts, no index wraps
-  // and no bound fails, so the shifted operand sits at a fixed offset from
-  // the unshifted one (the large core cell always qualifies).
-  bool fast = true;
+  // Fast path (uniform per wave).  Off circular axes a cell is one plane or
+  // the core segment, so a shift moves the whole cell box either inside the
+  // region (the core stays inside for every shift) or, on some axis,
+  // entirely outside it.  When each of the wave's shifts is one or the
+  // other, no index wraps and no bound is checked per point: a shift inside
+  // reads at a fixed offset from the unshifted operand, one outside
+  // contributes zeros.
+  bool fast = true, inb[DW];
   int64_t doff[DW];
 #pragma unroll
   for (int u = 0; u < DW; ++u) {
     doff[u] = ((int64_t)d[u][0] * a.d1 * a.d2 + (int64_t)d[u][1] * a.d2 + d[u][2]) * two_nc;
+    bool in = true, out = false;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax)
-      fast = fast && cst[ax] + d[u][ax] >= a.lo[ax] && cst[ax] + cln[ax] - 1 + d[u][ax] < a.hi[ax];
+    for (int ax = 0; ax < 3; ++ax) {
+      const int64_t b0 = cst[ax] + d[u][ax], b1 = cst[ax] + cln[ax] - 1 + d[u][ax];
+      in = in && b0 >= a.lo[ax] && b1 < a.hi[ax];
+      out = out || (a.per[ax] == 0 && (b1 < a.lo[ax] || b0 >= a.hi[ax]));
+    }
+    inb[u] = in && hok[u];
+    fast = fast && (in || out);
   }
   int64_t q = q_begin + g;
   int64_t p2 = q % cln[2], p1 = (q / cln[2]) % cln[1], p0 = q / (cln[2] * cln[1]);
   auto base_of = [&]() { return (((cst[0] + p0) * a.d1 + (cst[1] + p1)) * a.d2 + (cst[2] + p2)) * two_nc; };
   int64_t base = base_of();
   auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
-  auto fetch = [&](float (&av)[T], float (&bv)[DW][T]) {
-    const bool ok = q < q_end;
+  // The two paths get separate loops, so the fast one carries no wrap or
+  // bound logic.  Fast loads always issue (a masked-off lane reads element
+  // 0 and its value is replaced by zero), which keeps them unpredicated.
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto fetch = [&](float (&av)[T], float (&bv)[DW][T]) {
+      const bool ok = q < q_end;
+      if constexpr (FAST) {
 #pragma unroll
-    for (int i = 0; i < T; ++i) av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
-    if (fast) {
+        for (int i = 0; i < T; ++i) {
+          const bool on = ok && okc[i];
+          const float v = a.x[on ? base + 16 * i + m : 0];
+          av[i] = on ? v : 0.f;
+        }
 #pragma unroll
-      for (int u = 0; u < DW; ++u)
+        for (int u = 0; u < DW; ++u)
 #pragma unroll
-        for (int i = 0; i < T; ++i) bv[u][i] = (ok && hok[u] && okc[i]) ? a.x[base + doff[u] + 16 * i + m] : 0.f;
-    } else {
-      const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
+          for (int i = 0; i < T; ++i) {
+            const bool on = ok && inb[u] && okc[i];
+            const float v = a.x[on ? base + doff[u] + 16 * i + m : 0];
+            bv[u][i] = on ? v : 0.f;
+          }
+      } else {
 #pragma unroll
-      for (int u = 0; u < DW; ++u) {
-        const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
-                      v2 = wrap_to(w2 + d[u][2], a.per[2]);
-        const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
-                         v2 >= a.lo[2] && v2 < a.hi[2];
-        const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+        for (int i = 0; i < T; ++i) av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
+        const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
 #pragma unroll
-        for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
-      }
-    }
-    q += 4;
-    p2 += 4;
-    if (p2 < cln[2]) {
-      base += 4 * two_nc;
-    } else {
-      while (p2 >= cln[2]) {
-        p2 -= cln[2];
-        if (++p1 == cln[1]) {
-          p1 = 0;
-          ++p0;
+        for (int u = 0; u < DW; ++u) {
+          const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
+                        v2 = wrap_to(w2 + d[u][2], a.per[2]);
+          const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
+                           v2 >= a.lo[2] && v2 < a.hi[2];
+          const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+#pragma unroll
+          for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
         }
       }
-      base = base_of();
+      q += 4;
+      p2 += 4;
+      if (p2 < cln[2]) {
+        base += 4 * two_nc;
+      } else {
+        while (p2 >= cln[2]) {
+          p2 -= cln[2];
+          if (++p1 == cln[1]) {
+            p1 = 0;
+            ++p0;
+          }
+        }
+        base = base_of();
+      }
+    };
+    constexpr int PF = kGramAhead;
+    float av[PF][T], bv[PF][DW][T];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+    for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
+#pragma unroll
+      for (int r = 0; r < PF; ++r) {
+        if (q0 + 4 * r >= q_end) break;
+        double ad[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) ad[i] = (double)av[r][i];
+#pragma unroll
+        for (int u = 0; u < DW; ++u) {
+          double bd[T];
+#pragma unroll
+          for (int j = 0; j < T; ++j) bd[j] = (double)bv[r][u][j];
+#pragma unroll
+          for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j)
+              acc[u][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[u][i][j], 0, 0, 0);
+        }
+        fetch(av[r], bv[r]);  // the step PF positions further on
+      }
     }
   };
-  constexpr int PF = kGramAhead;
-  float av[PF][T], bv[PF][DW][T];
-#pragma unroll
-  for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
-  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
-#pragma unroll
-    for (int r = 0; r < PF; ++r) {
-      if (q0 + 4 * r >= q_end) break;
-      double ad[T];
-#pragma unroll
-      for (int i = 0; i < T; ++i) ad[i] = (double)av[r][i];
-#pragma unroll
-      for (int u = 0; u < DW; ++u) {
-        double bd[T];
-#pragma unroll
-        for (int j = 0; j < T; ++j) bd[j] = (double)bv[r][u][j];
-#pragma unroll
-        for (int i = 0; i < T; ++i)
-#pragma unroll
-          for (int j = 0; j < T; ++j)
-            acc[u][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[u][i][j], 0, 0, 0);
-      }
-      fetch(av[r], bv[r]);  // the step PF positions further on
-    }
-  }
+  if (fast) run(std::true_type{});
+  else run(std::false_type{});
   // v_mfma_f64_16x16x4: lane holds rows g, g + 4, g + 8, g + 12 of column m
 #pragma unroll
   for (int u = 0; u < DW; ++u) {
