@@ -488,7 +488,9 @@ def main():
                     help="comma list of fp32, bf16x3, bf16+refine, fp16+refine (volumes: fp32, bf16, fp16)")
     ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-routes", action="store_true", help="skip the rSVD-route solve of the 2-D workloads")
+    ap.add_argument("--no-routes", action="store_true", help="skip the solve on the other nullspace route")
+    ap.add_argument("--route", default="auto", choices=["auto", "gram", "rsvd"],
+                    help="nullspace route of the timed solves (auto: rsvd for the 2-D+t workloads, else gram)")
     ap.add_argument("--no-batch-tune", action="store_true", help="batched workload: keep the fixed shape rule")
     ap.add_argument("--no-volume", action="store_true",
                     help="skip the nested 256 x 320 x 320 x 8 volume gradient-step record")
@@ -564,7 +566,14 @@ def main():
 
     wrap = P.get("wrap")
 
-    def run(prec, refine, route="gram"):
+    # nullspace route of the timed paths: the rSVD for the 2-D+t workloads
+    # (the paper's route for that study, measured 3.5x faster there), the
+    # Gram eigendecomposition otherwise; the other route is timed as well
+    main_route = args.route if args.route != "auto" else ("rsvd" if args.workload.startswith("cine") else "gram")
+    alt_route = "gram" if main_route == "rsvd" else "rsvd"
+
+    def run(prec, refine, route=None):
+        route = main_route if route is None else route
         # the 2-D+t study starts from the time-averaged k-space (part of the timed work)
         xs = hicu.time_average_init(x0, mask, axis=0) if P.get("init") == "time_average" else x0
         return hicu.solve(xs, mask, kd, r, sched, p=P["p"], seed=P["seed"], prec=prec, refine_steps=refine, wrap=wrap,
@@ -596,33 +605,35 @@ def main():
                              final_J=trace[-1]["J"], sweeps=[t["sweeps"] for t in trace[::sched[0][2]]])
 
     # Nullspace routes (DISCUSSION: rSVD against the SVD of the Gram): the
-    # fastest path again with the randomized SVD + Householder update.
+    # bf16+refine path again with the other nullspace update.
     routes = None
     if not args.no_routes and n <= 2048:
         rpath = "bf16+refine" if "bf16+refine" in results else next(iter(results))
         rv = results[rpath]
         for _ in range(args.warmup):
-            run(rv["prec"], rv["refine"], "rsvd")
+            run(rv["prec"], rv["refine"], alt_route)
         torch.cuda.synchronize()
         hicu.profile_begin()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            xr, _ = run(rv["prec"], rv["refine"], "rsvd")
+            xr, _ = run(rv["prec"], rv["refine"], alt_route)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         rprof = hicu.profile_end()
-        _progress("%s, rsvd route: %.1f ms per solve" % (rpath, 1e3 * dt / args.steps))
+        _progress("%s, %s route: %.1f ms per solve" % (rpath, alt_route, 1e3 * dt / args.steps))
 
-        def null_ms(prof, keys):
+        def null_ms(prof, route):
+            keys = ("rsvd",) if route == "rsvd" else ("gram", "eig")
             return round(sum(prof[k]["total_ms"] for k in keys if k in prof) / args.steps, 3)
 
-        routes = dict(path=rpath, sketch=min(n, (3 * r + 1) // 2),
-                      gram=dict(ms_per_step=round(rv["ms_per_step"], 3), iters_per_s=round(rv["iters_per_s"], 3),
-                                ser_db=round(rv["ser"], 5), nullspace_ms=null_ms(rv["prof"], ("gram", "eig"))),
-                      rsvd=dict(ms_per_step=round(1e3 * dt / args.steps, 3),
-                                iters_per_s=round(args.steps * total_iters / dt, 3), ser_db=round(ser(xr), 5),
-                                d_ser_vs_gram=round(ser(xr) - rv["ser"], 5), nullspace_ms=null_ms(rprof, ("rsvd",)),
-                                kernel_ms={kk: round(vv["total_ms"] / args.steps, 3) for kk, vv in rprof.items()}))
+        main = dict(ms_per_step=round(rv["ms_per_step"], 3), iters_per_s=round(rv["iters_per_s"], 3),
+                    ser_db=round(rv["ser"], 5), nullspace_ms=null_ms(rv["prof"], main_route))
+        alt = dict(ms_per_step=round(1e3 * dt / args.steps, 3), iters_per_s=round(args.steps * total_iters / dt, 3),
+                   ser_db=round(ser(xr), 5), nullspace_ms=null_ms(rprof, alt_route),
+                   kernel_ms={kk: round(vv["total_ms"] / args.steps, 3) for kk, vv in rprof.items()})
+        alt["d_ser_vs_" + main_route] = round(ser(xr) - rv["ser"], 5)
+        routes = {"path": rpath, "sketch": min(n, (3 * r + 1) // 2), "timed_route": main_route,
+                  main_route: main, alt_route: alt}
         del xr
 
     # fixed SER: anchored on the FP64 oracle's reconstruction (on the FP32
@@ -644,7 +655,8 @@ def main():
                 config=dict(workload=args.workload, dims=list(P["x0"].shape[:3]), coils=int(P["x0"].shape[3]),
                             kernel=list(kd), rank=r, filters=p, outer=len(sched), inner=sched[0][2],
                             gradient_iters_per_step=total_iters, path=best, refine_steps=b["refine"],
-                            circular_axes=None if wrap is None else [int(w) for w in wrap], init=P.get("init")),
+                            circular_axes=None if wrap is None else [int(w) for w in wrap], init=P.get("init"),
+                            nullspace_route=main_route),
                 pts_filters_per_s=round(b["iters_per_s"] * s_out * p, 1),
                 paths={k: dict(iters_per_s=round(v["iters_per_s"], 3), ms_per_step=round(v["ms_per_step"], 3),
                                ser_db=round(v["ser"], 5), eig_sweeps=v["sweeps"],
