@@ -21,6 +21,7 @@
 // of range(Y) is used, so steps 3-4 give the V of a QR-based rSVD.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "eig.h"
 #include "ops.h"
@@ -118,53 +119,91 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
   // Lane group g walks positions q_begin + g, + 4, ...; (u0, u1, u2) follow q.
   int64_t q = q_begin + g;
   int64_t u2 = q % a.m2, u1 = (q / a.m2) % a.m1, u0 = q / (a.m2 * a.m1);
-  auto fetch = [&](float (&av)[2], float (&bv)[2]) {
-    const bool ok = q < q_end;
+  // Without circular axes the operand of row f sits at a fixed offset from
+  // the point's base in x (a tap) or in Y (a sketch column): the bases
+  // advance with the point and no index is wrapped or recomputed per step.
+  const bool wrap_any = a.per[0] != 0 || a.per[1] != 0 || a.per[2] != 0;
+  const float* src[2];
+  int64_t aoff[2];
+  bool ax_[2], on_[2];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      float v = 0.f;
-      if (ok && ra[f].kind == 0) {
-        const int64_t i0 = wrapped(a.lo[0] + u0 + ra[f].k0, a.per[0]);
-        const int64_t i1 = wrapped(a.lo[1] + u1 + ra[f].k1, a.per[1]);
-        const int64_t i2 = wrapped(a.lo[2] + u2 + ra[f].k2, a.per[2]);
-        v = a.x[((i0 * a.d1 + i1) * a.d2 + i2) * two_nc + ra[f].el];
-      } else if (ok && ra[f].kind == 1) {
-        v = a.Y[q * two_l + ra[f].col];
+  for (int f = 0; f < 2; ++f) {
+    ax_[f] = ra[f].kind == 0;
+    on_[f] = ra[f].kind != 2;
+    src[f] = ax_[f] ? a.x : a.Y;
+    aoff[f] = ax_[f] ? (((int64_t)ra[f].k0 * a.d1 + ra[f].k1) * a.d2 + ra[f].k2) * two_nc + ra[f].el
+                     : (int64_t)ra[f].col;
+  }
+  auto xbase_of = [&]() { return (((a.lo[0] + u0) * a.d1 + (a.lo[1] + u1)) * a.d2 + (a.lo[2] + u2)) * two_nc; };
+  int64_t xbase = xbase_of(), ybase = q * two_l;
+  auto run = [&](auto wrap_tag) {
+    constexpr bool WRAP = decltype(wrap_tag)::value;
+    auto fetch = [&](float (&av)[2], float (&bv)[2]) {
+      const bool ok = q < q_end;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        if constexpr (!WRAP) {
+          // the load always issues (a masked-off lane reads element 0)
+          const bool on = ok && on_[f];
+          const float v = src[f][on ? (ax_[f] ? xbase : ybase) + aoff[f] : 0];
+          av[f] = on ? v : 0.f;
+        } else {
+          float v = 0.f;
+          if (ok && ra[f].kind == 0) {
+            const int64_t i0 = wrapped(a.lo[0] + u0 + ra[f].k0, a.per[0]);
+            const int64_t i1 = wrapped(a.lo[1] + u1 + ra[f].k1, a.per[1]);
+            const int64_t i2 = wrapped(a.lo[2] + u2 + ra[f].k2, a.per[2]);
+            v = a.x[((i0 * a.d1 + i1) * a.d2 + i2) * two_nc + ra[f].el];
+          } else if (ok && ra[f].kind == 1) {
+            v = a.Y[ybase + ra[f].col];
+          }
+          av[f] = v;
+        }
+        const bool onb = ok && cb[f] >= 0;
+        const float w = a.Y[onb ? ybase + cb[f] : 0];
+        bv[f] = onb ? w : 0.f;
       }
-      av[f] = v;
-      bv[f] = (ok && cb[f] >= 0) ? a.Y[q * two_l + cb[f]] : 0.f;
-    }
-    q += 4;
-    u2 += 4;
-    while (u2 >= a.m2) {
-      u2 -= a.m2;
-      if (++u1 == a.m1) {
-        u1 = 0;
-        ++u0;
+      q += 4;
+      ybase += 4 * two_l;
+      u2 += 4;
+      if (u2 < a.m2) {
+        xbase += 4 * two_nc;
+      } else {
+        while (u2 >= a.m2) {
+          u2 -= a.m2;
+          if (++u1 == a.m1) {
+            u1 = 0;
+            ++u0;
+          }
+        }
+        xbase = xbase_of();
+      }
+    };
+    constexpr int PF = kProjAhead;
+    float av[PF][2], bv[PF][2];
+#pragma unroll
+    for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+    for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
+#pragma unroll
+      for (int r = 0; r < PF; ++r) {
+        if (q0 + 4 * r >= q_end) break;
+        double ad[2], bd[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          ad[f] = (double)av[r][f];
+          bd[f] = (double)bv[r][f];
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[f], bd[j], acc[f][j], 0, 0, 0);
+        fetch(av[r], bv[r]);
       }
     }
   };
-  constexpr int PF = kProjAhead;
-  float av[PF][2], bv[PF][2];
-#pragma unroll
-  for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
-  for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
-#pragma unroll
-    for (int r = 0; r < PF; ++r) {
-      if (q0 + 4 * r >= q_end) break;
-      double ad[2], bd[2];
-#pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        ad[f] = (double)av[r][f];
-        bd[f] = (double)bv[r][f];
-      }
-#pragma unroll
-      for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[f][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[f], bd[j], acc[f][j], 0, 0, 0);
-      fetch(av[r], bv[r]);
-    }
-  }
+  if (wrap_any) run(std::true_type{});
+  else run(std::false_type{});
 
   double* out = a.part + ((size_t)grp * a.ntiles + tile) * 4096;
 #pragma unroll
