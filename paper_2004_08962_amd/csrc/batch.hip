@@ -9,6 +9,7 @@
 
 #include "batch.h"
 #include "ops.h"
+#include "philox.h"
 #include "prof.h"
 #include "step.h"
 #include "tune.h"
@@ -41,51 +42,16 @@ struct ZeroItem {
   int active;
 };
 
-__device__ double philox_normal_b(int64_t e, uint64_t seed, uint32_t outer, uint32_t inner, uint32_t sid) {
-  uint32_t c[4] = {(uint32_t)(e >> 2), outer, inner, sid};
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[1] = (uint32_t)p1;
-    c[3] = (uint32_t)p0;
-    c[0] = n0;
-    c[2] = n2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  const int lane = (int)(e & 3);
-  const double two32 = 2.3283064365386963e-10;
-  const double ua = ((double)c[lane < 2 ? 0 : 2] + 0.5) * two32;
-  const double ub = ((double)c[lane < 2 ? 1 : 3] + 0.5) * two32;
-  const double R = sqrt(-2.0 * log(ua));
-  const double ang = 2.0 * 3.14159265358979323846 * ub;
-  return (lane & 1) ? R * sin(ang) : R * cos(ang);
-}
-
-// Block (j, q): column j of F_q = Q_q P_q with P_q drawn for the counter
-// (outer, inner) read from device memory and JL stream id q.
+// Block (j, b, q): column j, rows [64 b, 64 b + 64) of F_q = Q_q P_q with
+// P_q drawn for the counter (outer, inner) read from device memory and JL
+// stream id q -- the same draw and sums as the single-problem JL kernel.
 __global__ __launch_bounds__(256) void jl_batch_kernel(const JlItem* items, const uint32_t* counter) {
   extern __shared__ double pcol[];
-  const JlItem it = items[blockIdx.y];
-  const int j = blockIdx.x;
-  if (!it.active || j >= it.p) return;
-  const uint32_t outer = counter[0], inner = counter[1];
-  const double scale = 1.0 / sqrt((double)it.p);
-  for (int l = threadIdx.x; l < it.nq; l += blockDim.x)
-    pcol[l] = philox_normal_b((int64_t)l * it.p + j, it.seed, outer, inner, blockIdx.y) * scale;
-  __syncthreads();
-  for (int i = threadIdx.x; i < it.n; i += blockDim.x) {
-    double re = 0.0, im = 0.0;
-    const float2* q = it.Q + (size_t)i * it.nq;
-    for (int l = 0; l < it.nq; ++l) {
-      const float2 v = q[l];
-      re += (double)v.x * pcol[l];
-      im += (double)v.y * pcol[l];
-    }
-    it.F[(size_t)i * it.p + j] = make_float2((float)re, (float)im);
-  }
+  const JlItem it = items[blockIdx.z];
+  const int j = blockIdx.x, row0 = blockIdx.y * kJlRows;
+  if (!it.active || j >= it.p || row0 >= it.n) return;
+  jl_column_rows(it.Q, it.n, it.nq, it.p, j, row0, it.seed, counter[0], counter[1], blockIdx.z, pcol, it.F,
+                 nullptr);
 }
 
 __global__ __launch_bounds__(1024) void reduce_batch_kernel(const RedItem* items) {
@@ -410,8 +376,9 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
   uint32_t* counter = reinterpret_cast<uint32_t*>(at(ws, b->off_counter));
   if (b->any_jl) {
     ProfScope ps("jl", st);
-    hipLaunchKernelGGL(jl_batch_kernel, dim3(b->max_p, count), dim3(256), b->max_nq * sizeof(double), st,
-                       reinterpret_cast<const JlItem*>(at(ws, b->t_jl)), (const uint32_t*)counter);
+    hipLaunchKernelGGL(jl_batch_kernel, dim3(b->max_p, (unsigned)cdiv(b->max_n, kJlRows), count), dim3(256),
+                       b->max_nq * sizeof(double), st, reinterpret_cast<const JlItem*>(at(ws, b->t_jl)),
+                       (const uint32_t*)counter);
   }
   {
     ProfScope ps("prep_weights", st);
