@@ -15,8 +15,9 @@
 //     principal right singular vectors of B, largest first.
 //  5. Householder QR of V: reflector j is H_j = I - 2 w w' with w the unit
 //     vector along a - alpha e_j, a the j-th column of the partly reduced V
-//     from row j down and alpha = -exp(i arg a_0) ||a||.  The trailing
-//     n - r columns of H_1 ... H_r are Q.
+//     from row j down and alpha = -exp(i arg a_0) ||a||, formed a panel of
+//     up to 8 reflectors per launch.  The trailing n - r columns of
+//     H_1 ... H_r are Q.
 // Right singular vectors of U'H do not depend on which orthonormal basis U
 // of range(Y) is used, so steps 3-4 give the V of a QR-based rSVD.
 #include <algorithm>
@@ -325,47 +326,106 @@ __global__ __launch_bounds__(256) void top_kernel(const double2* E, const double
   Er[idx] = make_double2(e.x * s, e.y * s);
 }
 
-// Reflector j of the Householder QR of V (column-major, n x r) applied to
-// columns j + 1 ... of V: one wave per column, four per block.  Every wave
-// rebuilds the reflector from column j (which no wave writes in this
-// launch); block 0's first wave stores it in Wr (column j, rows j..n-1).
-__global__ __launch_bounds__(256) void hh_step_kernel(double2* V, int n, int r, int j, double2* Wr) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double2* a = V + (size_t)j * n;
-  double nr2 = 0.0;
-  for (int i = j + lane; i < n; i += 64) {
-    const double2 v = a[i];
-    nr2 += v.x * v.x + v.y * v.y;
+// Householder QR of V (column-major, n x r) in panels of b columns.  Every
+// block of a launch factors the panel (columns j0 .. j0 + b - 1 from row j0
+// down) in LDS -- the same arithmetic in every block, so all hold identical
+// reflectors -- then applies the b reflectors in order to its own trailing
+// columns (one wave per column, the column in registers, NPL values per
+// lane).  Block 0 stores the panel's unit reflector vectors in Wr.
+// Reflector jj: w along a - alpha e_jj with alpha = -ph ||a||, ph the phase
+// of a_0, so w_jj = ph (|a_0| + ||a||) and ||w||^2 = 2 ||a|| (||a|| + |a_0|).
+template <int NPL>
+__global__ __launch_bounds__(256) void hh_panel_kernel(double2* V, int n, int r, int j0, int b, double2* Wr) {
+  extern __shared__ double2 pan[];  // [b][len]
+  __shared__ double red[4];
+  __shared__ double2 sh_w0;
+  __shared__ double sh_inv;
+  const int len = n - j0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < b * len; e += 256) {
+    const int c = e / len, i = e - c * len;
+    pan[e] = V[(size_t)(j0 + c) * n + j0 + i];
   }
-  nr2 = warp_sum_d(nr2);
-  const double2 a0 = a[j];
-  const double norm = sqrt(nr2), mag0 = sqrt(a0.x * a0.x + a0.y * a0.y);
-  const double2 ph = mag0 > 0.0 ? make_double2(a0.x / mag0, a0.y / mag0) : make_double2(1.0, 0.0);
-  // w = a - alpha e_j with alpha = -ph ||a||: w_j = ph (|a_0| + ||a||),
-  // ||w||^2 = 2 ||a|| (||a|| + |a_0|)
-  const double2 w0 = make_double2(ph.x * (mag0 + norm), ph.y * (mag0 + norm));
-  const double wn2 = 2.0 * norm * (norm + mag0);
-  const double inv = wn2 > 0.0 ? 1.0 / sqrt(wn2) : 0.0;
-  auto w_at = [&](int i) {
-    const double2 v = i == j ? w0 : a[i];
-    return make_double2(v.x * inv, v.y * inv);
-  };
-  if (blockIdx.x == 0 && wave == 0)
-    for (int i = j + lane; i < n; i += 64) Wr[(size_t)j * n + i] = w_at(i);
-  const int c = j + 1 + blockIdx.x * 4 + wave;
+  __syncthreads();
+  for (int jj = 0; jj < b; ++jj) {
+    double2* a = pan + (size_t)jj * len;
+    double nr2 = 0.0;
+    for (int i = jj + tid; i < len; i += 256) nr2 += a[i].x * a[i].x + a[i].y * a[i].y;
+    nr2 = block_sum_d(nr2, red);
+    if (tid == 0) {
+      const double2 a0 = a[jj];
+      const double norm = sqrt(nr2), mag0 = sqrt(a0.x * a0.x + a0.y * a0.y);
+      const double2 ph = mag0 > 0.0 ? make_double2(a0.x / mag0, a0.y / mag0) : make_double2(1.0, 0.0);
+      sh_w0 = make_double2(ph.x * (mag0 + norm), ph.y * (mag0 + norm));
+      const double wn2 = 2.0 * norm * (norm + mag0);
+      sh_inv = wn2 > 0.0 ? 1.0 / sqrt(wn2) : 0.0;
+    }
+    __syncthreads();
+    const double inv = sh_inv;
+    for (int i = jj + tid; i < len; i += 256) {
+      const double2 v = i == jj ? sh_w0 : a[i];
+      a[i] = make_double2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+    for (int c = jj + 1 + wave; c < b; c += 4) {
+      double2* col = pan + (size_t)c * len;
+      double dr = 0.0, di = 0.0;
+      for (int i = jj + lane; i < len; i += 64) {
+        const double2 w = a[i], v = col[i];
+        dr += w.x * v.x + w.y * v.y;  // conj(w) v
+        di += w.x * v.y - w.y * v.x;
+      }
+      dr = warp_sum_d(dr);
+      di = warp_sum_d(di);
+      for (int i = jj + lane; i < len; i += 64) {
+        const double2 w = a[i], v = col[i];
+        col[i] = make_double2(v.x - 2.0 * (w.x * dr - w.y * di), v.y - 2.0 * (w.x * di + w.y * dr));
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0)
+    for (int e = tid; e < b * len; e += 256) {
+      const int c = e / len, i = e - c * len;
+      if (i >= c) Wr[(size_t)(j0 + c) * n + j0 + i] = pan[e];
+    }
+  const int c = j0 + b + blockIdx.x * 4 + wave;
   if (c >= r) return;
-  double2* col = V + (size_t)c * n;
-  double dr = 0.0, di = 0.0;
-  for (int i = j + lane; i < n; i += 64) {
-    const double2 w = w_at(i), v = col[i];
-    dr += w.x * v.x + w.y * v.y;  // conj(w) v
-    di += w.x * v.y - w.y * v.x;
+  double2* col = V + (size_t)c * n + j0;
+  double2 q[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int i = t * 64 + lane;
+    q[t] = i < len ? col[i] : make_double2(0.0, 0.0);
   }
-  dr = warp_sum_d(dr);
-  di = warp_sum_d(di);
-  for (int i = j + lane; i < n; i += 64) {
-    const double2 w = w_at(i), v = col[i];
-    col[i] = make_double2(v.x - 2.0 * (w.x * dr - w.y * di), v.y - 2.0 * (w.x * di + w.y * dr));
+  for (int jj = 0; jj < b; ++jj) {
+    const double2* w = pan + (size_t)jj * len;
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int i = t * 64 + lane;
+      if (i >= jj && i < len) {
+        const double2 wv = w[i];
+        dr += wv.x * q[t].x + wv.y * q[t].y;
+        di += wv.x * q[t].y - wv.y * q[t].x;
+      }
+    }
+    dr = warp_sum_d(dr);
+    di = warp_sum_d(di);
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int i = t * 64 + lane;
+      if (i >= jj && i < len) {
+        const double2 wv = w[i];
+        q[t].x -= 2.0 * (wv.x * dr - wv.y * di);
+        q[t].y -= 2.0 * (wv.x * di + wv.y * dr);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int i = t * 64 + lane;
+    if (i < len) col[i] = q[t];
   }
 }
 
@@ -476,6 +536,23 @@ int32_t launch_zgemm(int M, int N, int K, ZView A, ZView B, double2* C, int64_t 
                      hipStream_t st) {
   hipLaunchKernelGGL(zgemm_small_kernel, dim3((unsigned)cdiv(N, 16), (unsigned)cdiv(M, 16)), dim3(256), 0, st, M, N,
                      K, A, B, C, crs, ccs, herm ? 1 : 0);
+  HICU_HIP_TRY(hipGetLastError());
+  return HICU_OK;
+}
+
+// Panel width: up to 8 columns of at most 120 KB of LDS.
+int hh_panel_width(int n) { return (int)std::max<int64_t>(1, std::min<int64_t>(8, (120 << 10) / (16 * (int64_t)n))); }
+
+template <int NPL>
+int32_t launch_panels(double2* V, int n, int r, double2* Wr, hipStream_t st) {
+  const int bw = hh_panel_width(n);
+  for (int j0 = 0; j0 < r; j0 += bw) {
+    const int b = std::min(bw, r - j0);
+    const int cols = r - j0 - b;
+    const size_t lds = (size_t)b * (n - j0) * sizeof(double2);
+    hipLaunchKernelGGL(hh_panel_kernel<NPL>, dim3((unsigned)std::max<int64_t>(1, cdiv(cols, 4))), dim3(256), lds, st,
+                       V, n, r, j0, b, Wr);
+  }
   HICU_HIP_TRY(hipGetLastError());
   return HICU_OK;
 }
@@ -604,24 +681,24 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
   {
     ProfScope ps("householder", st);
     HICU_TRY(launch_zero(Wr, (size_t)n * rank * sizeof(double2), st));
-    for (int j = 0; j < rank; ++j) {
-      const int cols = rank - j - 1;
-      hipLaunchKernelGGL(hh_step_kernel, dim3((unsigned)std::max<int64_t>(1, cdiv(cols, 4))), dim3(256), 0, st, V, n,
-                         rank, j, Wr);
-    }
-    HICU_HIP_TRY(hipGetLastError());
     const int npl = (int)cdiv(n, 64);
     if (npl <= 2) {
+      HICU_TRY(launch_panels<2>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<2>(Wr, n, rank, Q, st));
     } else if (npl <= 4) {
+      HICU_TRY(launch_panels<4>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<4>(Wr, n, rank, Q, st));
     } else if (npl <= 8) {
+      HICU_TRY(launch_panels<8>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<8>(Wr, n, rank, Q, st));
     } else if (npl <= 16) {
+      HICU_TRY(launch_panels<16>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<16>(Wr, n, rank, Q, st));
     } else if (npl <= 24) {
+      HICU_TRY(launch_panels<24>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<24>(Wr, n, rank, Q, st));
     } else {
+      HICU_TRY(launch_panels<32>(V, n, rank, Wr, st));
       HICU_TRY(launch_apply<32>(Wr, n, rank, Q, st));
     }
   }
