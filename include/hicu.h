@@ -462,9 +462,11 @@ int32_t hicu_tune_put(const hicu_geom* geom, int32_t p, int32_t prec, int32_t ro
 
 /* The contraction kernels' tile shapes.  Shape `tile` covers T0 x 16 x
  * (T2 * D) output positions and 16 * WC * FN launch columns per workgroup
- * of four waves (wave grid (4 / WC) x WC; each wave an FM x FN grid of
- * 16 x 16 MFMA tiles); D > 1 packs D neighbouring outputs along the last
- * axis into the columns.  cfg receives int32[5] = {T0, T2, WC, FN, D}. */
+ * of four waves (wave grid (4 / (WC KS)) x WC x KS; each wave an FM x FN
+ * grid of 16 x 16 MFMA tiles); D > 1 packs D neighbouring outputs along
+ * the last axis into the columns; KS > 1 has KS waves share each
+ * fragment, taking every KS-th k-step, their sums added through LDS.
+ * cfg receives int32[6] = {T0, T2, WC, FN, D, KS}. */
 int32_t hicu_tile_count(void);
 int32_t hicu_tile_info(int32_t tile, int32_t* cfg);
 

@@ -104,8 +104,8 @@ def tune_put(shape, kdims, p, prec, role, tile, chunk, lo=None, hi=None):
 
 
 def tile_info(tile):
-    """(T0, T2, WC, FN, D) of shape id `tile`."""
-    cfg = (ctypes.c_int32 * 5)()
+    """(T0, T2, WC, FN, D, KS) of shape id `tile`."""
+    cfg = (ctypes.c_int32 * 6)()
     check(load().hicu_tile_info(int(tile), cfg), "hicu_tile_info")
     return tuple(cfg)
 

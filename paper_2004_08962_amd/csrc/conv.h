@@ -62,59 +62,75 @@ struct ConvArgs {
 
 // Tile shapes.  A block of 4 waves owns T0 positions along axis 0, 16
 // along axis 1 and T2*D along axis 2, and 16*WC*FN launch columns.  Its
-// T0*T2 row fragments (16 positions each) are split over 4/WC wave rows,
-// its column fragments over WC wave columns, so each wave accumulates an
-// FM x FN grid of 16 x 16 MFMA tiles (FM = T0*T2*WC/4).  D > 1 packs D
+// T0*T2 row fragments (16 positions each) are split over 4/(WC*KS) wave
+// rows, its column fragments over WC wave columns, so each wave
+// accumulates an FM x FN grid of 16 x 16 MFMA tiles (FM = T0*T2*WC*KS/4).
+// KS > 1 splits the k-steps instead: the KS waves of a group take every
+// KS-th k-step of each chunk for the same fragments, and their sums are
+// added through LDS in wave order before the epilogue (narrow outputs
+// then issue KS times more MFMAs per operand fetch and load each weight
+// fragment once per block).  D > 1 packs D
 // neighbouring outputs along axis 2 into the columns: launch column
 // delta*coutr + c is output column c at axis-2 offset delta, computed with
 // the kernel widened to k2 + D - 1 taps whose weights are shifted copies
 // (zero outside the original taps).  Narrow outputs (the adjoint has only
 // 2*coils real columns) then reuse every staged operand D times more.
 struct TileCfg {
-  int T0, T2, WC, FN, D;
+  int T0, T2, WC, FN, D, KS;
 };
 
-// X-macro list of the instantiated shapes: X(id, T0, T2, WC, FN, D, pipelined
-// staging available, batched kernel available).
+// X-macro list of the instantiated shapes: X(id, T0, T2, WC, FN, D, KS,
+// pipelined staging available, batched kernel available).
 #define HICU_TILES(X)            \
-  X(0, 1, 8, 1, 1, 1, 1, 1)      \
-  X(1, 1, 8, 1, 2, 1, 1, 1)      \
-  X(2, 1, 8, 1, 4, 1, 1, 1)      \
-  X(3, 1, 4, 1, 1, 1, 1, 1)      \
-  X(4, 1, 4, 1, 2, 1, 1, 1)      \
-  X(5, 1, 4, 1, 4, 1, 1, 1)      \
-  X(6, 1, 8, 2, 2, 1, 0, 0)      \
-  X(7, 1, 8, 2, 4, 1, 0, 0)      \
-  X(8, 1, 16, 2, 4, 1, 0, 0)     \
-  X(9, 1, 16, 1, 2, 1, 1, 1)     \
-  X(10, 1, 8, 1, 4, 2, 1, 0)     \
-  X(11, 1, 16, 1, 4, 2, 1, 0)    \
-  X(12, 1, 8, 1, 4, 4, 1, 0)     \
-  X(13, 2, 4, 1, 1, 1, 1, 1)     \
-  X(14, 2, 4, 1, 2, 1, 1, 1)     \
-  X(15, 2, 4, 1, 4, 1, 1, 1)     \
-  X(16, 2, 8, 1, 1, 1, 1, 0)     \
-  X(17, 2, 8, 1, 2, 1, 1, 0)     \
-  X(18, 2, 8, 1, 4, 1, 1, 0)     \
-  X(19, 2, 4, 2, 4, 1, 0, 0)     \
-  X(20, 2, 8, 2, 4, 1, 0, 0)     \
-  X(21, 2, 4, 1, 4, 4, 1, 0)     \
-  X(22, 2, 8, 1, 4, 4, 1, 0)     \
-  X(23, 2, 4, 1, 2, 2, 1, 0)     \
-  X(24, 2, 4, 1, 4, 2, 1, 0)     \
-  X(25, 2, 8, 1, 4, 2, 1, 0)      \
-  X(26, 4, 8, 1, 1, 1, 0, 0)      \
-  X(27, 8, 8, 1, 1, 1, 0, 0)      \
-  X(28, 4, 16, 1, 1, 1, 0, 0)     \
-  X(29, 8, 4, 1, 1, 1, 0, 0)      \
-  X(30, 4, 4, 2, 4, 1, 0, 0)      \
-  X(31, 8, 2, 1, 2, 2, 0, 0)      \
-  X(32, 8, 4, 1, 2, 2, 0, 0)      \
-  X(33, 4, 4, 1, 2, 2, 0, 0)      \
-  X(34, 2, 8, 2, 2, 1, 0, 0)      \
-  X(35, 4, 4, 2, 2, 1, 0, 0)
+  X(0, 1, 8, 1, 1, 1, 1, 1, 1)   \
+  X(1, 1, 8, 1, 2, 1, 1, 1, 1)   \
+  X(2, 1, 8, 1, 4, 1, 1, 1, 1)   \
+  X(3, 1, 4, 1, 1, 1, 1, 1, 1)   \
+  X(4, 1, 4, 1, 2, 1, 1, 1, 1)   \
+  X(5, 1, 4, 1, 4, 1, 1, 1, 1)   \
+  X(6, 1, 8, 2, 2, 1, 1, 0, 0)   \
+  X(7, 1, 8, 2, 4, 1, 1, 0, 0)   \
+  X(8, 1, 16, 2, 4, 1, 1, 0, 0)   \
+  X(9, 1, 16, 1, 2, 1, 1, 1, 1)   \
+  X(10, 1, 8, 1, 4, 2, 1, 1, 0)   \
+  X(11, 1, 16, 1, 4, 2, 1, 1, 0)   \
+  X(12, 1, 8, 1, 4, 4, 1, 1, 0)   \
+  X(13, 2, 4, 1, 1, 1, 1, 1, 1)   \
+  X(14, 2, 4, 1, 2, 1, 1, 1, 1)   \
+  X(15, 2, 4, 1, 4, 1, 1, 1, 1)   \
+  X(16, 2, 8, 1, 1, 1, 1, 1, 0)   \
+  X(17, 2, 8, 1, 2, 1, 1, 1, 0)   \
+  X(18, 2, 8, 1, 4, 1, 1, 1, 0)   \
+  X(19, 2, 4, 2, 4, 1, 1, 0, 0)   \
+  X(20, 2, 8, 2, 4, 1, 1, 0, 0)   \
+  X(21, 2, 4, 1, 4, 4, 1, 1, 0)   \
+  X(22, 2, 8, 1, 4, 4, 1, 1, 0)   \
+  X(23, 2, 4, 1, 2, 2, 1, 1, 0)   \
+  X(24, 2, 4, 1, 4, 2, 1, 1, 0)   \
+  X(25, 2, 8, 1, 4, 2, 1, 1, 0)   \
+  X(26, 4, 8, 1, 1, 1, 1, 0, 0)   \
+  X(27, 8, 8, 1, 1, 1, 1, 0, 0)   \
+  X(28, 4, 16, 1, 1, 1, 1, 0, 0)   \
+  X(29, 8, 4, 1, 1, 1, 1, 0, 0)   \
+  X(30, 4, 4, 2, 4, 1, 1, 0, 0)   \
+  X(31, 8, 2, 1, 2, 2, 1, 0, 0)   \
+  X(32, 8, 4, 1, 2, 2, 1, 0, 0)   \
+  X(33, 4, 4, 1, 2, 2, 1, 0, 0)   \
+  X(34, 2, 8, 2, 2, 1, 1, 0, 0)   \
+  X(35, 4, 4, 2, 2, 1, 1, 0, 0)   \
+  X(36, 1, 8, 1, 2, 1, 4, 1, 1)   \
+  X(37, 1, 8, 1, 1, 1, 4, 1, 1)   \
+  X(38, 2, 4, 1, 2, 1, 4, 1, 0)   \
+  X(39, 2, 4, 1, 1, 1, 4, 1, 0)   \
+  X(40, 4, 4, 1, 1, 1, 4, 1, 0)   \
+  X(41, 1, 4, 1, 2, 1, 4, 1, 1)   \
+  X(42, 1, 8, 1, 2, 1, 2, 1, 1)   \
+  X(43, 1, 4, 1, 4, 1, 4, 1, 0)   \
+  X(44, 4, 2, 1, 2, 2, 4, 0, 0)   \
+  X(45, 8, 2, 1, 2, 2, 2, 0, 0)   \
+  X(46, 4, 4, 1, 1, 1, 2, 1, 0)
 
-constexpr int kNumTiles = 36;
+constexpr int kNumTiles = 47;
 // Launch order: weights above kL2Resident bytes are walked one column block
 // at a time over runs of kTileRun position tiles.
 constexpr size_t kL2Resident = 2u << 20;
@@ -127,6 +143,13 @@ TileCfg tile_cfg(int id);
 bool tile_batch_ok(int id);
 // Block columns of a shape.
 inline int block_cols(const TileCfg& t) { return 16 * t.WC * t.FN; }
+// Row fragments per wave (FM) and the LDS bytes of a wave k-split's
+// reduction: each wave passes on the FM - FM / KS tiles (FN wide, 4 floats
+// per lane) that other waves of its group finish.
+inline int tile_fm(const TileCfg& t) { return t.T0 * t.T2 * t.WC * t.KS / 4; }
+inline size_t ks_reduce_bytes(const TileCfg& t) {
+  return (size_t)4 * (tile_fm(t) - tile_fm(t) / t.KS) * t.FN * 4 * 64 * sizeof(float);
+}
 
 struct ConvPlan {
   int prec;

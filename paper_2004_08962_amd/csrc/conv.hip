@@ -93,16 +93,16 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double* part, int64_
 // ---------------------------------------------------------------------------
 TileCfg tile_cfg(int id) {
   static const TileCfg table[kNumTiles] = {
-#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) {T0, T2, WC, FN, D},
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, KS, P, B) {T0, T2, WC, FN, D, KS},
       HICU_TILES(HICU_TILE_ROW)
 #undef HICU_TILE_ROW
   };
-  return (id >= 0 && id < kNumTiles) ? table[id] : TileCfg{0, 0, 0, 0, 0};
+  return (id >= 0 && id < kNumTiles) ? table[id] : TileCfg{0, 0, 0, 0, 0, 1};
 }
 
 bool tile_batch_ok(int id) {
   static const bool table[kNumTiles] = {
-#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) B != 0,
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, KS, P, B) B != 0,
       HICU_TILES(HICU_TILE_ROW)
 #undef HICU_TILE_ROW
   };
@@ -111,7 +111,7 @@ bool tile_batch_ok(int id) {
 
 static bool tile_pipe_ok(int id) {
   static const bool table[kNumTiles] = {
-#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, P, B) P != 0,
+#define HICU_TILE_ROW(id, T0, T2, WC, FN, D, KS, P, B) P != 0,
       HICU_TILES(HICU_TILE_ROW)
 #undef HICU_TILE_ROW
   };
@@ -222,12 +222,21 @@ int32_t launch_conv_batch(const BatchConvLaunch& b, hipStream_t st) {
 // 4 x 4 register tiles), 49.3 ms against 53.9 ms for 2 x 16 x 8 with one
 // wave column and 57.8 ms for 2 x 16 x 4 by 128; the line search over all
 // filters, which shares the shape, 43.5 against 47.9 ms.
+// The planar adjoint with two column fragments (32 real outputs) splits
+// the k-steps over the waves: on the 16-coil workload with 280 filters
+// the BF16 adjoint takes 97 us with 8 fragments per wave and KS = 4,
+// against 153 us for 2 fragments per wave; FP32 502 against 530 us; the
+// split BF16 pair, whose two operand sets make 8 x 2 fragments too many,
+// 166 us with KS = 2 against 232 us.  Volume adjoints keep their shapes:
+// there every k-split shape timed slower (48 ms and up on the 64-plane
+// slab against 32.4 ms).
 int default_tile(int prec, const Geo& g, int coutr, int role) {
   const bool is3d = g.k[0] > 1;
   const int frags = (int)cdiv(coutr, 16);
   if (role == 1) {
     if (is3d) return frags >= 3 ? 15 : (frags == 2 ? 14 : (prec == P_F32 ? 13 : (prec == P_BF16 ? 31 : 16)));
-    return frags >= 3 ? 2 : (frags == 2 ? 1 : 0);
+    if (frags == 2) return prec == P_BF16X3 ? 42 : (prec == P_F16 ? 1 : 36);
+    return frags >= 3 ? 2 : 0;
   }
   if (frags >= 8) return is3d ? (prec == P_BF16 ? 35 : 19) : (prec == P_F32 ? 6 : (prec == P_BF16X3 ? 2 : 7));
   if (frags >= 3) return is3d ? 15 : 2;
@@ -275,6 +284,8 @@ int32_t plan_conv(int prec, int tile, const int k[3], const WeightShape& ws, int
   a.rs = pick_rs(prec, need);
   const size_t esize = prec == P_F32 ? 4 : 2;
   plan->lds_bytes = (size_t)a.h[0] * a.h[1] * a.rs * esize * (prec == P_BF16X3 ? 2 : 1);
+  // wave k-split: the waves' partial tiles meet in LDS (after the last chunk)
+  if (t.KS > 1) plan->lds_bytes = std::max(plan->lds_bytes, ks_reduce_bytes(t));
   if (plan->lds_bytes > kMaxLds) return HICU_ERR_UNSUPPORTED;
   a.oe[0] = oe[0];
   a.oe[1] = oe[1];

@@ -280,15 +280,17 @@ __device__ __forceinline__ void stage_units(const ConvArgs& a, typename LdsElem<
 
 // One output tile: position tile bx (of gx) and column block by.  Shared by
 // the per-problem kernel and the persistent batched kernel.
-template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE, int YB = 0>
+template <int PREC, int T0, int T2, int WC, int FN, int D, int KS, bool PIPE, int YB = 0>
 __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, const int by, const int64_t gx,
                                           unsigned char* smem) {
   static_assert(YB == 0 || (PREC == P_BF16 && !PIPE), "compact residual: BF16, unpipelined");
   constexpr int KB = kblock_of(PREC);
   constexpr int NFRAG = T0 * T2;
-  constexpr int WR = 4 / WC;
-  static_assert(4 % WC == 0 && NFRAG % WR == 0, "tile must give each wave whole fragments");
+  constexpr int WR = 4 / (WC * KS);
+  static_assert(4 % (WC * KS) == 0 && NFRAG % WR == 0, "tile must give each wave whole fragments");
   constexpr int FM = NFRAG / WR;
+  static_assert(FM % KS == 0, "a k-split's epilogue gives each wave whole fragments");
+  constexpr int FE = FM / KS;  // fragments of this wave in the epilogue
   constexpr int BC = 16 * WC * FN;
   constexpr bool SPLIT = PREC == P_BF16X3;
   using E = typename LdsElem<PREC>::T;
@@ -298,7 +300,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   E* lds_lo = lds + lds_elems;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
-  const int wr = wave / WC, wc = wave % WC;
+  // wave = (wr * WC + wc) * KS + ks: ks picks the k-steps of a k-split
+  const int ks = wave % KS, wgrp = wave / KS, wr = wgrp / WC, wc = wgrp % WC;
   const int64_t t2i = bx % a.nt[2];
   const int64_t t1i = (bx / a.nt[2]) % a.nt[1];
   const int64_t t0i = bx / (a.nt[2] * a.nt[1]);
@@ -506,8 +509,43 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
       }
     }
   };
+  // Wave k-split: steps ks, ks + KS, ... of the chunk, operands one step
+  // ahead (A and B double buffered); the step's LDS shift is formed from its
+  // index (k0 h1 + k1) rs + t KB.
+  auto compute_chunk_ks = [&](const int chg) {
+    const BE* bhi0 = reinterpret_cast<const BE*>(a.B) + (size_t)chg * total * wstep;
+    const BE* blo0 = reinterpret_cast<const BE*>(a.Blo) + (size_t)chg * total * wstep;
+    auto shift_of = [&](const int i) {
+      const int t = i % nkb, kk = i / nkb;
+      return ((kk / nk1) * a.h[1] + kk % nk1) * a.rs + t * KB;
+    };
+    int i = ks;
+    if (i >= total) return;
+    FragA<PREC, FM> fa0, fa1;
+    FragB<PREC, FN> fb0, fb1;
+    load_b(fb0, bhi0 + (size_t)i * wstep, blo0 + (size_t)i * wstep);
+    load_a(fa0, shift_of(i));
+    for (;;) {
+      const int i1 = i + KS;
+      if (i1 < total) {
+        load_b(fb1, bhi0 + (size_t)i1 * wstep, blo0 + (size_t)i1 * wstep);
+        load_a(fa1, shift_of(i1));
+      }
+      mma(fa0, fb0);
+      if (i1 >= total) break;
+      const int i2 = i1 + KS;
+      if (i2 < total) {
+        load_b(fb0, bhi0 + (size_t)i2 * wstep, blo0 + (size_t)i2 * wstep);
+        load_a(fa0, shift_of(i2));
+      }
+      mma(fa1, fb1);
+      if (i2 >= total) break;
+      i = i2;
+    }
+  };
   auto compute_chunk = [&](const int chg) {
-    if constexpr (PIPE) compute_chunk_guarded(chg);
+    if constexpr (KS > 1) compute_chunk_ks(chg);
+    else if constexpr (PIPE) compute_chunk_guarded(chg);
     else compute_chunk_flat(chg);
   };
 
@@ -595,6 +633,50 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   // of each of its FM x FN tiles.  Launch column lc = delta * coutr + c.
   // Column terms are formed once per column, position terms once per
   // fragment; the four rows of a fragment step by one position along axis 1.
+  // A k-split's waves add their tiles in wave order; wave ks finishes
+  // fragments [ks FE, ks FE + FE) of its group.  Each wave passes the other
+  // owners' blocks through LDS (slot o - (o > w) of writer w for owner o)
+  // and keeps its own block in registers.
+  float4_t eacc[FE][FN];
+  if constexpr (KS == 1) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) eacc[f][j] = acc[f][j];
+  } else {
+    __syncthreads();  // every wave is done with the staged halo
+    float* red = reinterpret_cast<float*>(smem);
+    auto slot = [&](const int w, const int pos, const int fe, const int j, const int r) {
+      return ((((((wgrp * KS + w) * (KS - 1) + pos) * FE + fe) * FN + j) * 4 + r) * 64) + lane;
+    };
+#pragma unroll
+    for (int o = 0; o < KS; ++o) {
+      if (o == ks) continue;  // wave-uniform
+      const int pos = o - (o > ks ? 1 : 0);
+#pragma unroll
+      for (int fe = 0; fe < FE; ++fe)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[slot(ks, pos, fe, j, r)] = acc[o * FE + fe][j][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < KS; ++o) {
+      if (o != ks) continue;  // wave-uniform: register indices stay static
+#pragma unroll
+      for (int fe = 0; fe < FE; ++fe)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float v = 0.f;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) v += w == o ? acc[o * FE + fe][j][r] : red[slot(w, o - (o > w ? 1 : 0), fe, j, r)];
+            eacc[fe][j][r] = v;
+          }
+    }
+  }
   double ssq = 0.0;
   float vmax = 0.f;
   const int64_t r0 = base1 + 4 * g;  // axis-1 position of this lane's first row
@@ -615,8 +697,8 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
     }
   }
 #pragma unroll
-  for (int f = 0; f < FM; ++f) {
-    const int fg = wr * FM + f;
+  for (int f = 0; f < FE; ++f) {
+    const int fg = wr * FM + ks * FE + f;
     const int64_t p0 = base0 + fg / T2, p2b = base2 + (int64_t)(fg % T2) * D;
     const int64_t obase = p0 * a.os[0] + r0 * a.os[1] + p2b * a.os[2];
     const int64_t mbase = (a.morg[0] + p0) * a.ms[0] + (a.morg[1] + r0) * a.ms[1] + (a.morg[2] + p2b) * a.ms[2];
@@ -629,7 +711,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
       for (int i = 0; i < 4; ++i) {
         if (r0 + i >= a.oe[1]) continue;
         const bool masked = a.mask && a.mask[mb + i * a.ms[1]] != 0;
-        float v = masked ? 0.f : acc[f][j][i] * out_sc;
+        float v = masked ? 0.f : eacc[f][j][i] * out_sc;
         if (a.out) {
           const int64_t q = ob + i * a.os[1];
           if constexpr (YB == 2) {
@@ -682,14 +764,14 @@ __device__ __forceinline__ void split_work(const int64_t lin, const int64_t gx, 
   tile = first + (r - (int64_t)cb * width);
 }
 
-template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE, int YB = 0>
+template <int PREC, int T0, int T2, int WC, int FN, int D, int KS, bool PIPE, int YB = 0>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, int64_t gx, int gy, int run) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t lin = xcd_remap(blockIdx.x, gx * gy);
   int64_t tile;
   int cb;
   split_work(lin, gx, gy, run, tile, cb);
-  conv_tile<PREC, T0, T2, WC, FN, D, PIPE, YB>(a, tile, cb, gx, smem);
+  conv_tile<PREC, T0, T2, WC, FN, D, KS, PIPE, YB>(a, tile, cb, gx, smem);
 }
 
 // Persistent batched launch: the work list is every (position tile, column
@@ -697,7 +779,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a, int64_t gx, int g
 // q.  Workgroups stride over the list, so problems of any size and channel
 // count share one launch.  Each item runs the same tile code as the
 // per-problem kernel, so results are bitwise identical.
-template <int PREC, int T0, int T2, int WC, int FN, int D, bool PIPE>
+template <int PREC, int T0, int T2, int WC, int FN, int D, int KS, bool PIPE>
 __global__ __launch_bounds__(256) void conv_batch_kernel(const ConvArgs* args, const int64_t* tile_start, int nprob,
                                                          int64_t total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -711,7 +793,7 @@ __global__ __launch_bounds__(256) void conv_batch_kernel(const ConvArgs* args, c
     const ConvArgs& a = args[lo];
     const int64_t local = it - tile_start[lo];
     const int64_t gx = a.nt[0] * a.nt[1] * a.nt[2];
-    conv_tile<PREC, T0, T2, WC, FN, D, PIPE>(a, local % gx, (int)(local / gx), gx, smem);
+    conv_tile<PREC, T0, T2, WC, FN, D, KS, PIPE>(a, local % gx, (int)(local / gx), gx, smem);
     __syncthreads();  // the next item reuses LDS
   }
 }
@@ -721,16 +803,16 @@ template <int PREC>
 int32_t launch_prec_impl(const ConvPlan& p, bool pipe, hipStream_t st) {
   const dim3 grid((unsigned)(p.gx * p.gy)), block(256);
   switch (p.tile) {
-#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, P, B)                                                              \
+#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, KS, P, B)                                                            \
   case id:                                                                                                     \
     if constexpr (PREC == P_BF16 && T0 > 1) {                                                                  \
       if (p.a.yb == 1) {                                                                                       \
-        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false, 1>), grid, block, p.lds_bytes, st, p.a, \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, KS, false, 1>), grid, block, p.lds_bytes, st, p.a, \
                            p.gx, p.gy, p.run);                                                                 \
         break;                                                                                                 \
       }                                                                                                        \
       if (p.a.yb == 2) {                                                                                       \
-        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false, 2>), grid, block, p.lds_bytes, st, p.a, \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, KS, false, 2>), grid, block, p.lds_bytes, st, p.a, \
                            p.gx, p.gy, p.run);                                                                 \
         break;                                                                                                 \
       }                                                                                                        \
@@ -738,12 +820,12 @@ int32_t launch_prec_impl(const ConvPlan& p, bool pipe, hipStream_t st) {
     if (p.a.yb != 0) return HICU_ERR_UNSUPPORTED;                                                              \
     if constexpr (P != 0) {                                                                                    \
       if (pipe) {                                                                                              \
-        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, true>), grid, block, p.lds_bytes, st, p.a,     \
+        hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, KS, true>), grid, block, p.lds_bytes, st, p.a,     \
                            p.gx, p.gy, p.run);                                                                 \
         break;                                                                                                 \
       }                                                                                                        \
     }                                                                                                          \
-    hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, false>), grid, block, p.lds_bytes, st, p.a, p.gx,  \
+    hipLaunchKernelGGL((conv_kernel<PREC, T0, T2, WC, FN, D, KS, false>), grid, block, p.lds_bytes, st, p.a, p.gx,  \
                        p.gy, p.run);                                                                           \
     break;
     HICU_TILES(HICU_TILE_CASE)
@@ -758,14 +840,14 @@ template <int PREC>
 int32_t launch_batch_prec_impl(const BatchConvLaunch& b, hipStream_t st) {
   const dim3 grid(b.grid), block(256);
   switch (b.tile) {
-#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, P, B)                                                            \
+#define HICU_TILE_CASE(id, T0, T2, WC, FN, D, KS, P, B)                                                          \
   case id:                                                                                                   \
     if constexpr (B != 0) {                                                                                  \
       if (b.pipe)                                                                                            \
-        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, true>), grid, block, b.lds_bytes, st,  \
+        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, KS, true>), grid, block, b.lds_bytes, st,  \
                            b.args, b.tile_start, b.nprob, b.total);                                          \
       else                                                                                                   \
-        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, false>), grid, block, b.lds_bytes, st, \
+        hipLaunchKernelGGL((conv_batch_kernel<PREC, T0, T2, WC, FN, D, KS, false>), grid, block, b.lds_bytes, st, \
                            b.args, b.tile_start, b.nprob, b.total);                                          \
       break;                                                                                                 \
     }                                                                                                        \

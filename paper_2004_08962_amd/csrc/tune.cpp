@@ -276,6 +276,7 @@ int32_t hicu_tile_info(int32_t tile, int32_t* cfg) {
   cfg[2] = t.WC;
   cfg[3] = t.FN;
   cfg[4] = t.D;
+  cfg[5] = t.KS;
   return HICU_OK;
 }
 

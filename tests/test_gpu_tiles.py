@@ -56,7 +56,7 @@ def test_every_tile_shape(env, name, prec):
     bJ, bg = P["bounds"][prec]
     checked = 0
     for tile in range(hb.tile_count()):
-        T0, T2, WC, FN, D = hb.tile_info(tile)
+        T0, T2, WC, FN, D, KS = hb.tile_info(tile)
         if name == "2d" and T0 > 1:
             continue
         hb.tune_clear()
@@ -64,7 +64,7 @@ def test_every_tile_shape(env, name, prec):
             hb.tune_put(P["x"].shape, P["kd"], P["p"], prec, 0, tile, P["x"].shape[3], P["lo"], P["hi"])
         for chunk in (16, 4):
             hb.tune_put(P["x"].shape, P["kd"], P["p"], prec, 1, tile, chunk, P["lo"], P["hi"])
-            print(name, prec, "tile", tile, (T0, T2, WC, FN, D), "chunk", chunk, flush=True)
+            print(name, prec, "tile", tile, (T0, T2, WC, FN, D, KS), "chunk", chunk, flush=True)
             J, g, gn2 = hicu.objective_grad(x, mask, F, P["kd"], P["lo"], P["hi"], prec=prec)
             gh = g.cpu().numpy().astype(np.complex128)
             assert abs(J.item() - P["Jr"]) <= bJ, (tile, chunk)
@@ -100,13 +100,13 @@ def test_every_volume_tile_compact_residual():
     hicu.set_filter_group_budget(s * 4 * 64)  # groups of 64 + 6 filters
     try:
         for tile in range(hb.tile_count()):
-            T0, T2, WC, FN, D = hb.tile_info(tile)
+            T0, T2, WC, FN, D, KS = hb.tile_info(tile)
             if T0 == 1:
                 continue
             for chunk in (8, 4):
                 hb.tune_clear()
                 hb.tune_put(shape, kd, p, "bf16", 1, tile, chunk, lo, hi)
-                print("compact residual, tile", tile, (T0, T2, WC, FN, D), "chunk", chunk, flush=True)
+                print("compact residual, tile", tile, (T0, T2, WC, FN, D, KS), "chunk", chunk, flush=True)
                 J, g, gn2 = hicu.objective_grad(xd, md, Fd, kd, lo, hi, prec="bf16")
                 gh = g.cpu().numpy().astype(np.complex128)
                 assert abs(J.item() - Jr) <= bJ, (tile, chunk)
