@@ -119,10 +119,11 @@ __device__ __forceinline__ bool make_rot_fast(double a, double b, double2 c, dou
 // subproblem in LDS, U written to Ubuf[pair].  Each inner round: 16 lanes
 // compute the 16 rotations (skipping entries below the relative tolerance or
 // the absolute noise floor), then every thread produces one element of the
-// rotated S (double buffered) and one element of U.
+// rotated S (double buffered) and one element of U.  Sfin[pair] receives
+// the final diagonal 16-blocks of the subproblem.
 __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int npad, int nb, int round,
                                                         double tol, const double* floor_dev, double2* Ubuf,
-                                                        int* ident) {
+                                                        int* ident, double2* Sfin) {
   __shared__ double2 S[2][SB][SB + 1];
   __shared__ double2 U[2][SB][SB + 1];
   __shared__ Rot rot[SB / 2];
@@ -235,76 +236,352 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   if (total == 0) return;
   double2* out = Ubuf + (size_t)blockIdx.x * SB * SB;
   out[tid] = U[cur][tid >> 5][tid & 31];
+  // final diagonal 16-blocks of the subproblem, for the next round's pairs
+  if (tid < 512) {
+    const int blk = tid >> 8, i = (tid >> 4) & 15, j = tid & 15;
+    Sfin[(size_t)blockIdx.x * 512 + tid] = S[cur][blk * BS + i][blk * BS + j];
+  }
 }
 
-// Workgroup (alpha, beta): A[ia, ib] <- Ua^H A[ia, ib] Ub and
-// V[ia, ib] <- V[ia, ib] Ub, in place: the (alpha, beta) blocks partition
-// both matrices, so each element is read and written by one workgroup only.
-// Pairs whose subproblem needed no rotation have U = I and are skipped.
-// 1024 threads, one output element each.  With `sums`, the workgroup also
-// writes the squared Frobenius norms of the off-diagonal part and of its
-// whole block (indices < n) for the convergence test.
-__global__ __launch_bounds__(1024) void apply_kernel(double2* A, double2* V, int n, int npad, int nb, int round,
-                                                     const double2* Ubuf, const int* ident, double* sums) {
-  __shared__ double2 Bm[SB][SB + 1];
-  __shared__ double2 Vm[SB][SB + 1];
-  __shared__ double2 Ua[SB][SB + 1];
-  __shared__ double2 Ub[SB][SB + 1];
-  __shared__ int ia[SB], ib[SB];
-  __shared__ double red[16];
+// Index i (0..31) of pair `pair` in round r: its first 16-block, then its second.
+__device__ __forceinline__ int pair_index(int r, int nb, int pair, int i) {
+  const int P = r < 0 ? 2 * pair : circle_pos(pair, r, nb), Q = r < 0 ? 2 * pair + 1 : circle_pos(nb - 1 - pair, r, nb);
+  return i < BS ? P * BS + i : Q * BS + (i - BS);
+}
+
+// The pair holding 16-block X in round r and X's offset in it (0 or BS):
+// the inverse of the circle schedule.
+__device__ __forceinline__ void block_owner(int r, int nb, int X, int* pair, int* off) {
+  if (r < 0) {
+    *pair = X >> 1;
+    *off = (X & 1) * BS;
+    return;
+  }
+  const int m = nb - 1;
+  const int t = X == 0 ? 0 : 1 + (((X - 1 - r) % m) + m) % m;
+  *pair = t < nb / 2 ? t : nb - 1 - t;
+  *off = t < nb / 2 ? 0 : BS;
+}
+
+constexpr int kRoundThreads = 256;
+constexpr size_t kRoundLds = 48 * 1024;
+
+// Pair role of a round launch: solve round r's subproblem of pair `pair`
+// (blocks P, Q) without waiting for round r - 1's update of A.  Its four
+// 16 x 16 blocks of A^(r) = W'A^(r-1)W are formed here: the diagonal ones
+// are the final subproblem matrices of the round r - 1 pairs that held P
+// and Q (or A^(r-1) itself where such a pair did not rotate), the block
+// (P, Q) is Ux' A^(r-1)[I_x, I_y] Uy with I_x, I_y the index sets of those
+// pairs and Ux, Uy the 16 columns of their U that map to P and Q.
+//
+// The cross rotations then run with the subproblem in registers: thread
+// (a, b) = (tid / 16, tid % 16) holds the 2x2 block on rows (P a, Q s(a))
+// and columns (P b, Q s(b)), s(x) = (x + k) mod 16 at inner round k, so
+// that rotation t of round k (indices P t and Q s(t)) acts on thread row t
+// and thread column t only; between inner rounds s advances by one and the
+// Q parts move one thread row / column through LDS.  U rows likewise:
+// thread (i, c) = (tid / 8, tid % 8) holds U[i][P t] and U[i][Q s(t)] for
+// t = 2c, 2c + 1.  Outputs: U (unless no rotation was needed), the
+// identity flag, and the final diagonal 16-blocks for the next round.
+__device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair, const double2* Ucur,
+                          const int* idcur, const double2* Scur, double2* Unext, int* idnext, double2* Snext,
+                          double tol, double fl, unsigned char* lds) {
   const int tid = threadIdx.x;
-  const int alpha = blockIdx.x, beta = blockIdx.y;
-  const bool ida = ident[alpha] != 0, idb = ident[beta] != 0;
-  if (ida && idb && !sums) return;
-  if (tid == 0) block_indices(round, nb, alpha, ia);
-  if (tid == 1) block_indices(round, nb, beta, ib);
-  __syncthreads();
-  const int r = tid >> 5, c = tid & 31;
-  const int gi = ia[r], gj = ib[c];
-  double2 out = A[(size_t)gi * npad + gj];
-  if (!(ida && idb)) {
-    const double2* ua = Ubuf + (size_t)alpha * SB * SB;
-    const double2* ub = Ubuf + (size_t)beta * SB * SB;
-    Ua[r][c] = ida ? make_double2(r == c ? 1.0 : 0.0, 0.0) : ua[tid];
-    Ub[r][c] = idb ? make_double2(r == c ? 1.0 : 0.0, 0.0) : ub[tid];
-    Bm[r][c] = out;
-    if (!idb) Vm[r][c] = V[(size_t)gi * npad + gj];
-    __syncthreads();
-    if (!ida) {  // T = Ua^H B
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 8
-      for (int k = 0; k < SB; ++k) acc = cadd(acc, cmulc(Ua[k][r], Bm[k][c]));
-      out = acc;
-      __syncthreads();
-      Bm[r][c] = out;
-      __syncthreads();
+  const int a = tid >> 4, b = tid & 15;
+  const int P = circle_pos(pair, r, nb), Q = circle_pos(nb - 1 - pair, r, nb);
+  int pp, op, pq, oq;
+  block_owner(r - 1, nb, P, &pp, &op);
+  block_owner(r - 1, nb, Q, &pq, &oq);
+  const bool idp = idcur[pp] != 0, idq = idcur[pq] != 0;
+  double2 stt, sbb, stb, sbt;
+  {
+    auto M = reinterpret_cast<double2(*)[SB + 1]>(lds);                       // 32 x 33
+    auto Ux = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 33 * 16);       // 32 x 17
+    auto Uy = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 50 * 16);       // 32 x 17
+    auto L = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 67 * 16);        // 32 x 17
+    auto C = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 84 * 16);        // 16 x 17
+    for (int e = tid; e < SB * SB; e += kRoundThreads) {
+      const int i = e >> 5, j = e & 31;
+      M[i][j] = Ain[(size_t)pair_index(r - 1, nb, pp, i) * npad + pair_index(r - 1, nb, pq, j)];
     }
-    if (!idb) {  // out = T Ub, V <- V Ub
-      double2 acc = make_double2(0.0, 0.0), vacc = make_double2(0.0, 0.0);
+    for (int e = tid; e < SB * BS; e += kRoundThreads) {
+      const int k = e >> 4, j = e & 15;
+      Ux[k][j] = idp ? make_double2(k == op + j ? 1.0 : 0.0, 0.0) : Ucur[(size_t)pp * SB * SB + k * SB + op + j];
+      Uy[k][j] = idq ? make_double2(k == oq + j ? 1.0 : 0.0, 0.0) : Ucur[(size_t)pq * SB * SB + k * SB + oq + j];
+    }
+    stt = idp ? Ain[(size_t)(P * BS + a) * npad + P * BS + b] : Scur[(size_t)pp * 512 + (op ? 256 : 0) + a * BS + b];
+    sbb = idq ? Ain[(size_t)(Q * BS + a) * npad + Q * BS + b] : Scur[(size_t)pq * 512 + (oq ? 256 : 0) + a * BS + b];
+    __syncthreads();
+    {  // L = M Uy (32 x 16), two entries per thread
+      const int i = tid >> 3, j0 = (tid & 7) * 2;
+      double2 l0 = make_double2(0.0, 0.0), l1 = l0;
 #pragma unroll 8
       for (int k = 0; k < SB; ++k) {
-        acc = cadd(acc, cmul(Bm[r][k], Ub[k][c]));
-        vacc = cadd(vacc, cmul(Vm[r][k], Ub[k][c]));
+        const double2 mv = M[i][k];
+        l0 = cadd(l0, cmul(mv, Uy[k][j0]));
+        l1 = cadd(l1, cmul(mv, Uy[k][j0 + 1]));
       }
-      out = acc;
-      V[(size_t)gi * npad + gj] = vacc;
+      L[i][j0] = l0;
+      L[i][j0 + 1] = l1;
     }
-    A[(size_t)gi * npad + gj] = out;
+    __syncthreads();
+    {  // C = Ux' L (16 x 16)
+      double2 cv = make_double2(0.0, 0.0);
+#pragma unroll 8
+      for (int k = 0; k < SB; ++k) cv = cadd(cv, cmulc(Ux[k][a], L[k][b]));
+      C[a][b] = cv;
+    }
+    __syncthreads();
+    stb = C[a][b];
+    sbt = cconj(C[b][a]);
+    __syncthreads();  // the LDS is reused below
+  }
+  auto Xtb = reinterpret_cast<double2(*)[BS + 1]>(lds);
+  auto Xbt = reinterpret_cast<double2(*)[BS + 1]>(lds + 16 * 17 * 16);
+  auto Xbb = reinterpret_cast<double2(*)[BS + 1]>(lds + 2 * 16 * 17 * 16);
+  auto Xu = reinterpret_cast<double2(*)[BS + 1]>(lds + 3 * 16 * 17 * 16);   // 32 x 17
+  double* rcs = reinterpret_cast<double*>(lds + 5 * 16 * 17 * 16);
+  double* rsn = rcs + BS;
+  double2* re = reinterpret_cast<double2*>(rsn + BS);
+  double* dg = reinterpret_cast<double*>(re + BS);
+  int* flag = reinterpret_cast<int*>(dg + SB);
+  if (tid == 0) flag[0] = 0;
+  if (a == b) {
+    dg[a] = stt.x;
+    dg[BS + a] = sbb.x;
+  }
+  __syncthreads();
+  {
+    // early exit when no cross entry is above the rotation thresholds
+    const double v2 = stb.x * stb.x + stb.y * stb.y;
+    if (v2 > fl * fl && v2 > tol * tol * fabs(dg[a] * dg[BS + b])) flag[0] = 1;
+  }
+  __syncthreads();
+  if (flag[0] == 0) {
+    if (tid == 0) idnext[pair] = 1;
+    return;
+  }
+  const int ui = tid >> 3, uc = tid & 7;
+  double2 ut[2], ub[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int t = 2 * uc + k;
+    ut[k] = make_double2(ui == t ? 1.0 : 0.0, 0.0);
+    ub[k] = make_double2(ui == BS + t ? 1.0 : 0.0, 0.0);
+  }
+  int nrot = 0;
+  for (int k = 0; k < BS; ++k) {
+    if (a == b) {
+      Rot ro;
+      nrot += make_rot_fast(stt.x, sbb.x, stb, tol, fl, &ro);
+      rcs[a] = ro.cs;
+      rsn[a] = ro.sn;
+      re[a] = ro.e;
+    }
+    __syncthreads();
+    Rot ra, rb;
+    ra.cs = rcs[a];
+    ra.sn = rsn[a];
+    ra.e = re[a];
+    rb.cs = rcs[b];
+    rb.sn = rsn[b];
+    rb.e = re[b];
+    rot2x2(ra, rb, stt, stb, sbt, sbb);
+    if (a == b && ra.sn != 0.0) {
+      stb = sbt = make_double2(0.0, 0.0);
+      stt.y = sbb.y = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      // U <- U J for pair t: new P = cs uP - sn conj(e) uQ, new Q = sn uP + cs conj(e) uQ
+      const int t = 2 * uc + j;
+      const double cs = rcs[t], sn = rsn[t];
+      const double2 w = cmul(ub[j], cconj(re[t]));
+      const double2 up = ut[j];
+      ut[j] = cadd(csc(cs, up), csc(-sn, w));
+      ub[j] = cadd(csc(sn, up), csc(cs, w));
+    }
+    if (k == BS - 1) break;
+    Xtb[a][b] = stb;
+    Xbt[a][b] = sbt;
+    Xbb[a][b] = sbb;
+    Xu[ui][2 * uc] = ub[0];
+    Xu[ui][2 * uc + 1] = ub[1];
+    __syncthreads();
+    const int a1 = (a + 1) & 15, b1 = (b + 1) & 15;
+    stb = Xtb[a][b1];
+    sbt = Xbt[a1][b];
+    sbb = Xbb[a1][b1];
+    ub[0] = Xu[ui][(2 * uc + 1) & 15];
+    ub[1] = Xu[ui][(2 * uc + 2) & 15];
+  }
+  // After inner round 15 the Q parts sit at s(x) = x + 15.
+  __syncthreads();
+  if (tid == 0) flag[1] = 0;
+  __syncthreads();
+  if (nrot) atomicAdd(&flag[1], nrot);
+  __syncthreads();
+  const int tot = flag[1];
+  if (tid == 0) idnext[pair] = tot == 0;
+  if (tot == 0) return;
+  double2* out = Unext + (size_t)pair * SB * SB + (size_t)ui * SB;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = 2 * uc + j;
+    out[t] = ut[j];
+    out[BS + ((t + BS - 1) & 15)] = ub[j];
+  }
+  double2* sf = Snext + (size_t)pair * 512;
+  sf[a * BS + b] = stt;
+  sf[256 + ((a + BS - 1) & 15) * BS + ((b + BS - 1) & 15)] = sbb;
+}
+
+// Apply role: the block update of round r on the FP64 matrix cores.  One
+// workgroup per unordered pair alpha <= beta of index pairs: Aout[ia, ib]
+// = Ua' Ain[ia, ib] Ub and, for alpha < beta, its mirror Aout[ib, ia] =
+// Aout[ia, ib]'; V[ia, ib] <- V[ia, ib] Ub and V[ib, ia] <- V[ib, ia] Ua in
+// place.  Wave (ti, tj) owns the 16 x 16 tiles (ti, tj) of T = Ua' B
+// (exchanged through LDS), of T Ub and of the V blocks.  Complex products
+// are four real v_mfma_f64_16x16x4 per k-step of 4 (operand of lane (g, m)
+// = (lane / 16, lane % 16): A[m][4c + g] and B[4c + g][m]; the result holds
+// rows g + 4v of column m).  Operands come straight from global memory
+// (identity for pairs that did not rotate, whose U was not written).  With
+// `sums`, squared Frobenius norms of the off-diagonal part and of the
+// whole of both blocks (indices < n).
+__device__ void apply_role(const double2* Ain, double2* Aout, double2* V, int n, int npad, int nb, int npair, int r,
+                           int task, const double2* Ubuf, const int* ident, double* sums, unsigned char* lds) {
+  auto Ttr = reinterpret_cast<double(*)[SB + 2]>(lds);
+  auto Tti = reinterpret_cast<double(*)[SB + 2]>(lds + SB * (SB + 2) * 8);
+  double* red = reinterpret_cast<double*>(lds + 2 * SB * (SB + 2) * 8);
+  int alpha = 0, rem = task;
+  while (rem >= npair - alpha) {
+    rem -= npair - alpha;
+    ++alpha;
+  }
+  const int beta = alpha + rem;
+  const bool ida = ident[alpha] != 0, idb = ident[beta] != 0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
+  const double2* ua = Ubuf + (size_t)alpha * SB * SB;
+  const double2* ub = Ubuf + (size_t)beta * SB * SB;
+  auto uval = [&](const double2* u, bool id, int k, int j) {
+    return id ? make_double2(k == j ? 1.0 : 0.0, 0.0) : u[k * SB + j];
+  };
+  auto mma = [](double x, double y, double4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); };
+  const int ti = wave >> 1, tj = wave & 1;
+  const int im = ti * BS + m, jm = tj * BS + m;
+  {
+    // T = Ua' B, B = Ain[ia, ib]: A operand conj(Ua[k][im]), B operand B[k][jm]
+    const size_t col = (size_t)pair_index(r, nb, beta, jm);
+    double2 av[8], bv[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int k = 4 * c + g;
+      av[c] = uval(ua, ida, k, im);
+      bv[c] = Ain[(size_t)pair_index(r, nb, alpha, k) * npad + col];
+    }
+    double4_t tr = {0.0, 0.0, 0.0, 0.0}, tm = tr;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      tr = mma(av[c].x, bv[c].x, tr);
+      tr = mma(av[c].y, bv[c].y, tr);
+      tm = mma(av[c].x, bv[c].y, tm);
+      tm = mma(-av[c].y, bv[c].x, tm);
+    }
+    // stored k-major for the next product: Tt[k][i] = T[i][k]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ttr[jm][ti * BS + g + 4 * v] = tr[v];
+      Tti[jm][ti * BS + g + 4 * v] = tm[v];
+    }
+  }
+  // V tiles: the two waves of a tile row read the whole row stripe, so the
+  // in-place results are stored only after the barrier below.
+  auto vtile = [&](int pr, int pc, const double2* u, double4_t& orr, double4_t& oi) {
+    const size_t row = (size_t)pair_index(r, nb, pr, im) * npad;
+    double2 av[8], bv[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int k = 4 * c + g;
+      av[c] = V[row + pair_index(r, nb, pc, k)];
+      bv[c] = u[k * SB + jm];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      orr = mma(av[c].x, bv[c].x, orr);
+      orr = mma(-av[c].y, bv[c].y, orr);
+      oi = mma(av[c].x, bv[c].y, oi);
+      oi = mma(av[c].y, bv[c].x, oi);
+    }
+  };
+  auto vstore = [&](int pr, int pc, const double4_t& orr, const double4_t& oi) {
+    const int gc = pair_index(r, nb, pc, jm);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      V[(size_t)pair_index(r, nb, pr, ti * BS + g + 4 * v) * npad + gc] = make_double2(orr[v], oi[v]);
+  };
+  const bool v1 = !idb, v2 = alpha < beta && !ida;
+  double4_t o1r = {0.0, 0.0, 0.0, 0.0}, o1i = o1r, o2r = o1r, o2i = o1r;
+  if (v1) vtile(alpha, beta, ub, o1r, o1i);
+  if (v2) vtile(beta, alpha, ua, o2r, o2i);
+  __syncthreads();
+  if (v1) vstore(alpha, beta, o1r, o1i);
+  if (v2) vstore(beta, alpha, o2r, o2i);
+  // O = T Ub: A operand T[im][k] = Tt[k][im], B operand Ub[k][jm]
+  double4_t orr = {0.0, 0.0, 0.0, 0.0}, oi = orr;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int k = 4 * c + g;
+    const double2 bb = uval(ub, idb, k, jm);
+    const double ar = Ttr[k][im], ai = Tti[k][im];
+    orr = mma(ar, bb.x, orr);
+    orr = mma(-ai, bb.y, orr);
+    oi = mma(ar, bb.y, oi);
+    oi = mma(ai, bb.x, oi);
+  }
+  double off2 = 0.0, all2 = 0.0;
+  const int gc = pair_index(r, nb, beta, jm);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gr = pair_index(r, nb, alpha, ti * BS + g + 4 * v);
+    const double2 o = make_double2(orr[v], oi[v]);
+    Aout[(size_t)gr * npad + gc] = o;
+    if (alpha < beta) Aout[(size_t)gc * npad + gr] = cconj(o);
+    if (gr < n && gc < n) {
+      const double e2 = o.x * o.x + o.y * o.y;
+      all2 += e2;
+      if (gr != gc) off2 += e2;
+    }
   }
   if (sums) {
-    double off2 = 0.0, all2 = 0.0;
-    if (gi < n && gj < n) {
-      all2 = out.x * out.x + out.y * out.y;
-      if (gi != gj) off2 = all2;
+    const double w = alpha < beta ? 2.0 : 1.0;  // the mirror block
+    off2 = warp_sum_d(off2 * w);
+    all2 = warp_sum_d(all2 * w);
+    if (lane == 0) {
+      red[wave] = off2;
+      red[4 + wave] = all2;
     }
-    off2 = block_sum_d(off2, red);
-    all2 = block_sum_d(all2, red);
+    __syncthreads();
     if (tid == 0) {
-      const size_t slot = (size_t)alpha * gridDim.y + beta;
-      sums[2 * slot] = off2;
-      sums[2 * slot + 1] = all2;
+      sums[2 * task] = (red[0] + red[1]) + (red[2] + red[3]);
+      sums[2 * task + 1] = (red[4] + red[5]) + (red[6] + red[7]);
     }
   }
+}
+
+// One launch per round: workgroups [0, npr) solve round r_apply + 1's
+// subproblems (npr = npair, or 0 for the last round of a sweep), the rest
+// apply round r_apply's rotations (Ain -> Aout, V in place).  Both roles
+// read only what earlier launches wrote, so they need no ordering between
+// them.
+__global__ __launch_bounds__(kRoundThreads) void round_kernel(
+    const double2* Ain, double2* Aout, double2* V, int n, int npad, int nb, int npair, int r_apply, int npr,
+    const double2* Ucur, const int* idcur, const double2* Scur, double2* Unext, int* idnext, double2* Snext,
+    double tol, const double* floor_dev, double* sums) {
+  __shared__ __align__(16) unsigned char lds[kRoundLds];
+  if ((int)blockIdx.x < npr)
+    pair_role(Ain, npad, nb, r_apply + 1, blockIdx.x, Ucur, idcur, Scur, Unext, idnext, Snext, tol, *floor_dev, lds);
+  else
+    apply_role(Ain, Aout, V, n, npad, nb, npair, r_apply, blockIdx.x - npr, Ucur, idcur, sums, lds);
 }
 
 // Fixed-order sum of the per-block convergence partials: out = {off^2, all^2}.
@@ -382,14 +659,22 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const double2* X, const doub
 }
 
 // Ascending order of the n real eigenvalues (ties by index): perm[rank] = i.
-__global__ void rank_kernel(const double2* A, int n, int npad, int* perm, double* vals) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double li = A[(size_t)i * npad + i].x;
-    int rk = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = A[(size_t)j * npad + j].x;
-      rk += (lj < li) || (lj == li && j < i);
+__global__ __launch_bounds__(256) void rank_kernel(const double2* A, int n, int npad, int* perm, double* vals) {
+  __shared__ double dgl[1024];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double li = i < n ? A[(size_t)i * npad + i].x : 0.0;
+  int rk = 0;
+  for (int j0 = 0; j0 < n; j0 += 1024) {
+    const int cnt = min(1024, n - j0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) dgl[j] = A[(size_t)(j0 + j) * npad + j0 + j].x;
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const double lj = dgl[j];
+      rk += (lj < li) || (lj == li && j0 + j < i);
     }
+  }
+  if (i < n) {
     perm[rk] = i;
     vals[rk] = li;
   }
@@ -432,7 +717,7 @@ static int npad_of(int n) { return (int)rup(n, SB); }
 
 namespace {
 struct EigLayout {
-  size_t A, V, T, U, ident, part, perm, vals, sums, total;
+  size_t A, A2, V, T, U, ident, S, part, perm, vals, sums, total;
 };
 EigLayout eig_layout(int n) {
   const size_t np = (size_t)npad_of(n), npair = np / SB;
@@ -445,10 +730,12 @@ EigLayout eig_layout(int n) {
     return o;
   };
   L.A = take(mat);
+  L.A2 = take(mat);
   L.V = take(mat);
   L.T = take(mat);
-  L.U = take(npair * SB * SB * sizeof(double2));
-  L.ident = take(npair * sizeof(int));
+  L.U = take(2 * npair * SB * SB * sizeof(double2));
+  L.ident = take(2 * npair * sizeof(int));
+  L.S = take(2 * npair * 2 * BS * BS * sizeof(double2));
   L.part = take(2 * npair * npair * sizeof(double));
   L.perm = take(np * sizeof(int));
   L.vals = take(np * sizeof(double));
@@ -465,14 +752,19 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   const double floor_rel = projector_only ? 1e-13 : 2e-15;
   const EigLayout L = eig_layout(n);
   if (ws == nullptr || ws_bytes < L.total) return HICU_ERR_WORKSPACE;
-  const int np = npad_of(n), nb = np / BS, npair = nb / 2;
+  const int np = npad_of(n), nb = np / BS, npair = nb / 2, nwg = npair * (npair + 1) / 2;
   const size_t mat = (size_t)np * np;
   char* base = reinterpret_cast<char*>(ws);
-  double2* A = reinterpret_cast<double2*>(base + L.A);
+  double2* Abuf[2] = {reinterpret_cast<double2*>(base + L.A), reinterpret_cast<double2*>(base + L.A2)};
+  double2* A = Abuf[0];
   double2* V = reinterpret_cast<double2*>(base + L.V);
   double2* T = reinterpret_cast<double2*>(base + L.T);
-  double2* Ub = reinterpret_cast<double2*>(base + L.U);
-  int* ident = reinterpret_cast<int*>(base + L.ident);
+  // per-round outputs of the pair solves, double buffered by round parity
+  double2* Ubuf[2] = {reinterpret_cast<double2*>(base + L.U),
+                      reinterpret_cast<double2*>(base + L.U) + (size_t)npair * SB * SB};
+  int* idbuf[2] = {reinterpret_cast<int*>(base + L.ident), reinterpret_cast<int*>(base + L.ident) + npair};
+  double2* Sbuf[2] = {reinterpret_cast<double2*>(base + L.S),
+                      reinterpret_cast<double2*>(base + L.S) + (size_t)npair * 2 * BS * BS};
   double* part = reinterpret_cast<double*>(base + L.part);
   int* perm = reinterpret_cast<int*>(base + L.perm);
   double* vals = reinterpret_cast<double*>(base + L.vals);
@@ -498,20 +790,25 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   int sweeps = 0;
   double sums[2] = {0.0, 0.0}, prev = INFINITY;
   int32_t status = HICU_OK;
+  // Round r's pair outputs go to buffer (r + 2) % 2.  A sweep is the
+  // opening round's pair solves, then nb - 1 launches that each apply round
+  // r - 1 (A[cur] -> A[cur ^ 1]) while solving round r, then the last apply.
+  auto par = [](int r) { return (r + 2) & 1; };
+  int cur = 0;
   for (;;) {
     // opening round: blocks (2 j, 2 j + 1) with all their index pairs
-    hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)A, np, nb, -1, tol_inner,
-                       (const double*)dfloor, Ub, ident);
-    hipLaunchKernelGGL(apply_kernel, dim3(npair, npair), dim3(1024), 0, st, A, V, n, np, nb, -1, (const double2*)Ub,
-                       (const int*)ident, (double*)nullptr);
-    for (int r = 0; r < nb - 1; ++r) {
-      const bool last = r == nb - 2;
-      hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)A, np, nb, r, tol_inner,
-                         (const double*)dfloor, Ub, ident);
-      hipLaunchKernelGGL(apply_kernel, dim3(npair, npair), dim3(1024), 0, st, A, V, n, np, nb, r,
-                         (const double2*)Ub, (const int*)ident, last ? part : nullptr);
+    hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)Abuf[cur], np, nb, -1,
+                       tol_inner, (const double*)dfloor, Ubuf[par(-1)], idbuf[par(-1)], Sbuf[par(-1)]);
+    for (int r = 0; r <= nb - 1; ++r) {
+      const bool last = r == nb - 1;  // apply only
+      const int npr = last ? 0 : npair;
+      hipLaunchKernelGGL(round_kernel, dim3(npr + nwg), dim3(kRoundThreads), 0, st, (const double2*)Abuf[cur],
+                         Abuf[cur ^ 1], V, n, np, nb, npair, r - 1, npr, (const double2*)Ubuf[par(r - 1)],
+                         (const int*)idbuf[par(r - 1)], (const double2*)Sbuf[par(r - 1)], Ubuf[par(r)],
+                         idbuf[par(r)], Sbuf[par(r)], tol_inner, (const double*)dfloor, last ? part : nullptr);
+      cur ^= 1;
     }
-    hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, npair * npair, dsums);
+    hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nwg, dsums);
     HICU_HIP_TRY(hipGetLastError());
     ++sweeps;
     HICU_HIP_TRY(hipMemcpyAsync(sums, dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -530,6 +827,7 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   }
   if (sweeps_out) *sweeps_out = sweeps;
   if (status == HICU_ERR_NONFINITE) return status;
+  A = Abuf[cur];
   hipLaunchKernelGGL(rank_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, (const double2*)A, n, np,
                      perm, vals);
   hipLaunchKernelGGL(gather_kernel, dim3(n), dim3(256), 0, st, (const double2*)V, n, np, n - rank,
