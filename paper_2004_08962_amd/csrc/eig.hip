@@ -292,7 +292,10 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
   int pp, op, pq, oq;
   block_owner(r - 1, nb, P, &pp, &op);
   block_owner(r - 1, nb, Q, &pq, &oq);
-  const bool idp = idcur[pp] != 0, idq = idcur[pq] != 0;
+  // Every operand is loaded before the identity flags are known (the U and
+  // final-block buffers of a pair that did not rotate hold stale but
+  // in-bounds values, replaced below), so the loads overlap.
+  const int idp_raw = idcur[pp], idq_raw = idcur[pq];
   double2 stt, sbb, stb, sbt;
   {
     auto M = reinterpret_cast<double2(*)[SB + 1]>(lds);                       // 32 x 33
@@ -300,36 +303,56 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     auto Uy = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 50 * 16);       // 32 x 17
     auto L = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 67 * 16);        // 32 x 17
     auto C = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 84 * 16);        // 16 x 17
-    for (int e = tid; e < SB * SB; e += kRoundThreads) {
-      const int i = e >> 5, j = e & 31;
-      M[i][j] = Ain[(size_t)pair_index(r - 1, nb, pp, i) * npad + pair_index(r - 1, nb, pq, j)];
+    double2 mv[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = tid + h * kRoundThreads, i = e >> 5, j = e & 31;
+      mv[h] = Ain[(size_t)pair_index(r - 1, nb, pp, i) * npad + pair_index(r - 1, nb, pq, j)];
     }
-    for (int e = tid; e < SB * BS; e += kRoundThreads) {
-      const int k = e >> 4, j = e & 15;
-      Ux[k][j] = idp ? make_double2(k == op + j ? 1.0 : 0.0, 0.0) : Ucur[(size_t)pp * SB * SB + k * SB + op + j];
-      Uy[k][j] = idq ? make_double2(k == oq + j ? 1.0 : 0.0, 0.0) : Ucur[(size_t)pq * SB * SB + k * SB + oq + j];
+    double2 ux[2], uy[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * kRoundThreads, k = e >> 4, j = e & 15;
+      ux[h] = Ucur[(size_t)pp * SB * SB + k * SB + op + j];
+      uy[h] = Ucur[(size_t)pq * SB * SB + k * SB + oq + j];
     }
-    stt = idp ? Ain[(size_t)(P * BS + a) * npad + P * BS + b] : Scur[(size_t)pp * 512 + (op ? 256 : 0) + a * BS + b];
-    sbb = idq ? Ain[(size_t)(Q * BS + a) * npad + Q * BS + b] : Scur[(size_t)pq * 512 + (oq ? 256 : 0) + a * BS + b];
+    const double2 att = Ain[(size_t)(P * BS + a) * npad + P * BS + b];
+    const double2 abb = Ain[(size_t)(Q * BS + a) * npad + Q * BS + b];
+    const double2 ftt = Scur[(size_t)pp * 512 + (op ? 256 : 0) + a * BS + b];
+    const double2 fbb = Scur[(size_t)pq * 512 + (oq ? 256 : 0) + a * BS + b];
+    const bool idp = idp_raw != 0, idq = idq_raw != 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * kRoundThreads, k = e >> 4, j = e & 15;
+      Ux[k][j] = idp ? make_double2(k == op + j ? 1.0 : 0.0, 0.0) : ux[h];
+      Uy[k][j] = idq ? make_double2(k == oq + j ? 1.0 : 0.0, 0.0) : uy[h];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = tid + h * kRoundThreads;
+      M[e >> 5][e & 31] = mv[h];
+    }
+    stt = idp ? att : ftt;
+    sbb = idq ? abb : fbb;
     __syncthreads();
-    {  // L = M Uy (32 x 16), two entries per thread
+    {  // L = M Uy (32 x 16), two entries per thread; even and odd k summed apart
       const int i = tid >> 3, j0 = (tid & 7) * 2;
-      double2 l0 = make_double2(0.0, 0.0), l1 = l0;
-#pragma unroll 8
+      double2 l0[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)}, l1[2] = {l0[0], l0[0]};
+#pragma unroll
       for (int k = 0; k < SB; ++k) {
         const double2 mv = M[i][k];
-        l0 = cadd(l0, cmul(mv, Uy[k][j0]));
-        l1 = cadd(l1, cmul(mv, Uy[k][j0 + 1]));
+        l0[k & 1] = cadd(l0[k & 1], cmul(mv, Uy[k][j0]));
+        l1[k & 1] = cadd(l1[k & 1], cmul(mv, Uy[k][j0 + 1]));
       }
-      L[i][j0] = l0;
-      L[i][j0 + 1] = l1;
+      L[i][j0] = cadd(l0[0], l0[1]);
+      L[i][j0 + 1] = cadd(l1[0], l1[1]);
     }
     __syncthreads();
     {  // C = Ux' L (16 x 16)
-      double2 cv = make_double2(0.0, 0.0);
-#pragma unroll 8
-      for (int k = 0; k < SB; ++k) cv = cadd(cv, cmulc(Ux[k][a], L[k][b]));
-      C[a][b] = cv;
+      double2 cv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+#pragma unroll
+      for (int k = 0; k < SB; ++k) cv[k & 1] = cadd(cv[k & 1], cmulc(Ux[k][a], L[k][b]));
+      C[a][b] = cadd(cv[0], cv[1]);
     }
     __syncthreads();
     stb = C[a][b];
@@ -631,33 +654,40 @@ __global__ void init_kernel(const double2* G, const double2* V0, int n, int npad
   }
 }
 
-// C = op(X) Y for npad x npad complex matrices; op = conj-transpose when ct.
+// C = op(X) Y for npad x npad complex matrices (op = conj-transpose when
+// ct) on the FP64 matrix cores: one wave per 16 x 16 tile of C, four real
+// v_mfma_f64_16x16x4 per k-step of 4 (lane (g, m) supplies op(X)[i0 + m]
+// [k + g] and Y[k + g][j0 + m]), operands read from global memory eight
+// k-steps ahead.
 __global__ __launch_bounds__(256) void zgemm_kernel(const double2* X, const double2* Y, double2* C, int npad,
                                                     int ct) {
-  __shared__ double2 Xs[32][33];
-  __shared__ double2 Ys[32][33];
-  const int tid = threadIdx.x;
-  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
-  const int r = tid >> 3, c0 = (tid & 7) * 4;
-  double2 acc[4];
-  for (int c = 0; c < 4; ++c) acc[c] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < npad; k0 += 32) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int i = e / 32, j = e % 32;
-      // Xs[i][kk] = op(X)[bi + i][k0 + kk]
-      Xs[i][j] = ct ? cconj(X[(size_t)(k0 + j) * npad + bi + i]) : X[(size_t)(bi + i) * npad + k0 + j];
-      Ys[i][j] = Y[(size_t)(k0 + i) * npad + bj + j];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
+  const int i0 = blockIdx.y * 32 + (wave >> 1) * 16, j0 = blockIdx.x * 32 + (wave & 1) * 16;
+  auto xval = [&](int k) {
+    return ct ? cconj(X[(size_t)k * npad + i0 + m]) : X[(size_t)(i0 + m) * npad + k];
+  };
+  double4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+  constexpr int U = 8;
+  for (int k0 = 0; k0 < npad; k0 += 4 * U) {
+    double2 av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 4 * u + g;
+      const bool in = k < npad;
+      av[u] = in ? xval(k) : make_double2(0.0, 0.0);
+      bv[u] = in ? Y[(size_t)k * npad + j0 + m] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    for (int k = 0; k < 32; ++k) {
-      const double2 xv = Xs[r][k];
-      for (int c = 0; c < 4; ++c) acc[c] = cadd(acc[c], cmul(xv, Ys[k][c0 + c]));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].x, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u].y, bv[u].y, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x, ci, 0, 0, 0);
     }
-    __syncthreads();
   }
-  for (int c = 0; c < 4; ++c) C[(size_t)(bi + r) * npad + bj + c0 + c] = acc[c];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(size_t)(i0 + g + 4 * v) * npad + j0 + m] = make_double2(cr[v], ci[v]);
 }
-
 // Ascending order of the n real eigenvalues (ties by index): perm[rank] = i.
 __global__ __launch_bounds__(256) void rank_kernel(const double2* A, int n, int npad, int* perm, double* vals) {
   __shared__ double dgl[1024];
