@@ -279,10 +279,12 @@ constexpr size_t kRoundLds = 48 * 1024;
 // and columns (P b, Q s(b)), s(x) = (x + k) mod 16 at inner round k, so
 // that rotation t of round k (indices P t and Q s(t)) acts on thread row t
 // and thread column t only; between inner rounds s advances by one and the
-// Q parts move one thread row / column through LDS.  U rows likewise:
-// thread (i, c) = (tid / 8, tid % 8) holds U[i][P t] and U[i][Q s(t)] for
-// t = 2c, 2c + 1.  Outputs: U (unless no rotation was needed), the
-// identity flag, and the final diagonal 16-blocks for the next round.
+// Q parts move one thread row / column through LDS.  Thread (a, b) also
+// holds U[i][P a] and U[i][Q s(a)] for rows i = b, b + 16, so it needs
+// rotations a and b only, which it forms itself from the published
+// diagonal blocks (one barrier per inner round).  Outputs: U (unless no
+// rotation was needed), the identity flag, and the final diagonal
+// 16-blocks for the next round.
 __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair, const double2* Ucur,
                           const int* idcur, const double2* Scur, double2* Unext, int* idnext, double2* Snext,
                           double tol, double fl, unsigned char* lds) {
@@ -359,100 +361,109 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     sbt = cconj(C[b][a]);
     __syncthreads();  // the LDS is reused below
   }
-  auto Xtb = reinterpret_cast<double2(*)[BS + 1]>(lds);
-  auto Xbt = reinterpret_cast<double2(*)[BS + 1]>(lds + 16 * 17 * 16);
-  auto Xbb = reinterpret_cast<double2(*)[BS + 1]>(lds + 2 * 16 * 17 * 16);
-  auto Xu = reinterpret_cast<double2(*)[BS + 1]>(lds + 3 * 16 * 17 * 16);   // 32 x 17
-  double* rcs = reinterpret_cast<double*>(lds + 5 * 16 * 17 * 16);
-  double* rsn = rcs + BS;
-  double2* re = reinterpret_cast<double2*>(rsn + BS);
-  double* dg = reinterpret_cast<double*>(re + BS);
-  int* flag = reinterpret_cast<int*>(dg + SB);
-  if (tid == 0) flag[0] = 0;
+  // Exchange buffers, double buffered by inner round parity (one barrier
+  // per round: a round's writes go to the buffer the previous round's reads
+  // did not use).  Per buffer: the Q parts of S, the Q parts of U (two rows
+  // per thread) and the P-P diagonal entries.
+  constexpr int kXB = 16 * 17 * 16;  // bytes of one 16 x 17 double2 array
+  constexpr int kXSet = 5 * kXB + 16 * 8;
+  auto xtb = [&](int p) { return reinterpret_cast<double2(*)[BS + 1]>(lds + p * kXSet); };
+  auto xbt = [&](int p) { return reinterpret_cast<double2(*)[BS + 1]>(lds + p * kXSet + kXB); };
+  auto xbb = [&](int p) { return reinterpret_cast<double2(*)[BS + 1]>(lds + p * kXSet + 2 * kXB); };
+  auto xu = [&](int p, int h) { return reinterpret_cast<double2(*)[BS + 1]>(lds + p * kXSet + (3 + h) * kXB); };
+  auto xd = [&](int p) { return reinterpret_cast<double*>(lds + p * kXSet + 5 * kXB); };
+  double* d0a = reinterpret_cast<double*>(lds + 2 * kXSet);
+  double* d0b = d0a + BS;
+  double2* d0c = reinterpret_cast<double2*>(d0b + BS);
+  int* flag = reinterpret_cast<int*>(d0c + BS);
+  if (tid == 0) {
+    flag[0] = 0;
+    flag[1] = 0;
+  }
   if (a == b) {
-    dg[a] = stt.x;
-    dg[BS + a] = sbb.x;
+    d0a[a] = stt.x;
+    d0b[a] = sbb.x;
+    d0c[a] = stb;
   }
   __syncthreads();
+  // rotation inputs of indices a and b (diagonal 2x2 blocks of round 0)
+  double aa = d0a[a], ba = d0b[a], ab = d0a[b], bb = d0b[b];
+  double2 ca = d0c[a], cb = d0c[b];
   {
     // early exit when no cross entry is above the rotation thresholds
     const double v2 = stb.x * stb.x + stb.y * stb.y;
-    if (v2 > fl * fl && v2 > tol * tol * fabs(dg[a] * dg[BS + b])) flag[0] = 1;
+    if (v2 > fl * fl && v2 > tol * tol * fabs(aa * bb)) flag[0] = 1;
   }
   __syncthreads();
   if (flag[0] == 0) {
     if (tid == 0) idnext[pair] = 1;
     return;
   }
-  const int ui = tid >> 3, uc = tid & 7;
+  // Thread (a, b) also holds U rows b and b + 16 at P a and Q s(a).
   double2 ut[2], ub[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int t = 2 * uc + k;
-    ut[k] = make_double2(ui == t ? 1.0 : 0.0, 0.0);
-    ub[k] = make_double2(ui == BS + t ? 1.0 : 0.0, 0.0);
+  for (int h = 0; h < 2; ++h) {
+    ut[h] = make_double2(b + BS * h == a ? 1.0 : 0.0, 0.0);
+    ub[h] = make_double2(b + BS * h == BS + a ? 1.0 : 0.0, 0.0);
   }
   int nrot = 0;
+  const int a1 = (a + 1) & 15, b1 = (b + 1) & 15;
   for (int k = 0; k < BS; ++k) {
-    if (a == b) {
-      Rot ro;
-      nrot += make_rot_fast(stt.x, sbb.x, stb, tol, fl, &ro);
-      rcs[a] = ro.cs;
-      rsn[a] = ro.sn;
-      re[a] = ro.e;
-    }
-    __syncthreads();
+    // every thread forms the two rotations it uses (identical arithmetic
+    // on identical inputs in every thread)
     Rot ra, rb;
-    ra.cs = rcs[a];
-    ra.sn = rsn[a];
-    ra.e = re[a];
-    rb.cs = rcs[b];
-    rb.sn = rsn[b];
-    rb.e = re[b];
+    const bool did = make_rot_fast(aa, ba, ca, tol, fl, &ra);
+    make_rot_fast(ab, bb, cb, tol, fl, &rb);
+    if (a == b) nrot += did;
     rot2x2(ra, rb, stt, stb, sbt, sbb);
-    if (a == b && ra.sn != 0.0) {
+    if (a == b && did) {
       stb = sbt = make_double2(0.0, 0.0);
       stt.y = sbb.y = 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      // U <- U J for pair t: new P = cs uP - sn conj(e) uQ, new Q = sn uP + cs conj(e) uQ
-      const int t = 2 * uc + j;
-      const double cs = rcs[t], sn = rsn[t];
-      const double2 w = cmul(ub[j], cconj(re[t]));
-      const double2 up = ut[j];
-      ut[j] = cadd(csc(cs, up), csc(-sn, w));
-      ub[j] = cadd(csc(sn, up), csc(cs, w));
+    for (int h = 0; h < 2; ++h) {
+      // U <- U J for pair a: new P = cs uP - sn conj(e) uQ, new Q = sn uP + cs conj(e) uQ
+      const double2 w = cmul(ub[h], cconj(ra.e));
+      const double2 up = ut[h];
+      ut[h] = cadd(csc(ra.cs, up), csc(-ra.sn, w));
+      ub[h] = cadd(csc(ra.sn, up), csc(ra.cs, w));
     }
     if (k == BS - 1) break;
-    Xtb[a][b] = stb;
-    Xbt[a][b] = sbt;
-    Xbb[a][b] = sbb;
-    Xu[ui][2 * uc] = ub[0];
-    Xu[ui][2 * uc + 1] = ub[1];
+    const int pb = k & 1;
+    xtb(pb)[a][b] = stb;
+    xbt(pb)[a][b] = sbt;
+    xbb(pb)[a][b] = sbb;
+    xu(pb, 0)[a][b] = ub[0];
+    xu(pb, 1)[a][b] = ub[1];
+    if (a == b) xd(pb)[a] = stt.x;
     __syncthreads();
-    const int a1 = (a + 1) & 15, b1 = (b + 1) & 15;
-    stb = Xtb[a][b1];
-    sbt = Xbt[a1][b];
-    sbb = Xbb[a1][b1];
-    ub[0] = Xu[ui][(2 * uc + 1) & 15];
-    ub[1] = Xu[ui][(2 * uc + 2) & 15];
+    // s advances by one: Q parts from thread row / column + 1
+    stb = xtb(pb)[a][b1];
+    sbt = xbt(pb)[a1][b];
+    sbb = xbb(pb)[a1][b1];
+    ub[0] = xu(pb, 0)[a1][b];
+    ub[1] = xu(pb, 1)[a1][b];
+    // diagonal block of index t after the shift: P-P entry unchanged,
+    // P-Q entry from block (t, t + 1), Q-Q entry from block (t + 1, t + 1)
+    aa = xd(pb)[a];
+    ca = xtb(pb)[a][a1];
+    ba = xbb(pb)[a1][a1].x;
+    ab = xd(pb)[b];
+    cb = xtb(pb)[b][b1];
+    bb = xbb(pb)[b1][b1].x;
   }
   // After inner round 15 the Q parts sit at s(x) = x + 15.
-  __syncthreads();
-  if (tid == 0) flag[1] = 0;
-  __syncthreads();
   if (nrot) atomicAdd(&flag[1], nrot);
   __syncthreads();
   const int tot = flag[1];
   if (tid == 0) idnext[pair] = tot == 0;
   if (tot == 0) return;
-  double2* out = Unext + (size_t)pair * SB * SB + (size_t)ui * SB;
+  double2* out = Unext + (size_t)pair * SB * SB;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int t = 2 * uc + j;
-    out[t] = ut[j];
-    out[BS + ((t + BS - 1) & 15)] = ub[j];
+  for (int h = 0; h < 2; ++h) {
+    const int i = b + BS * h;
+    out[i * SB + a] = ut[h];
+    out[i * SB + BS + ((a + BS - 1) & 15)] = ub[h];
   }
   double2* sf = Snext + (size_t)pair * 512;
   sf[a * BS + b] = stt;
