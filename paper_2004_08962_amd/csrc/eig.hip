@@ -264,7 +264,7 @@ __device__ __forceinline__ void block_owner(int r, int nb, int X, int* pair, int
 }
 
 constexpr int kRoundThreads = 256;
-constexpr size_t kRoundLds = 48 * 1024;
+constexpr size_t kRoundLds = 56 * 1024;
 
 // Pair role of a round launch: solve round r's subproblem of pair `pair`
 // (blocks P, Q) without waiting for round r - 1's update of A.  Its four
@@ -303,8 +303,8 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     auto M = reinterpret_cast<double2(*)[SB + 1]>(lds);                       // 32 x 33
     auto Ux = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 33 * 16);       // 32 x 17
     auto Uy = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 50 * 16);       // 32 x 17
-    auto L = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 67 * 16);        // 32 x 17
-    auto C = reinterpret_cast<double2(*)[BS + 1]>(lds + 32 * 84 * 16);        // 16 x 17
+    auto LP = reinterpret_cast<double2(*)[SB][BS + 1]>(lds + 32 * 67 * 16);   // 2 x 32 x 17
+    auto CP = reinterpret_cast<double2(*)[BS][BS]>(lds);                      // 4 x 16 x 16, over M
     double2 mv[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -337,28 +337,46 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     stt = idp ? att : ftt;
     sbb = idq ? abb : fbb;
     __syncthreads();
-    {  // L = M Uy (32 x 16), two entries per thread; even and odd k summed apart
-      const int i = tid >> 3, j0 = (tid & 7) * 2;
-      double2 l0[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)}, l1[2] = {l0[0], l0[0]};
+    // On the matrix cores (lane (g, m) = (lane / 16, lane % 16) supplies
+    // A[m][4c + g] and B[4c + g][m]; results hold rows g + 4v of column m).
+    // L = M Uy: wave w forms row tile w & 1 over k-half w >> 1.
+    const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
+    auto mma = [](double x, double y, double4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); };
+    {
+      const int rt = wave & 1, kh = wave >> 1;
+      double4_t lr = {0.0, 0.0, 0.0, 0.0}, li = lr;
 #pragma unroll
-      for (int k = 0; k < SB; ++k) {
-        const double2 mv = M[i][k];
-        l0[k & 1] = cadd(l0[k & 1], cmul(mv, Uy[k][j0]));
-        l1[k & 1] = cadd(l1[k & 1], cmul(mv, Uy[k][j0 + 1]));
+      for (int c = 0; c < 4; ++c) {
+        const int k = (kh * 4 + c) * 4 + g;
+        const double2 av = M[rt * BS + m][k], bv = Uy[k][m];
+        lr = mma(av.x, bv.x, lr);
+        lr = mma(-av.y, bv.y, lr);
+        li = mma(av.x, bv.y, li);
+        li = mma(av.y, bv.x, li);
       }
-      L[i][j0] = cadd(l0[0], l0[1]);
-      L[i][j0 + 1] = cadd(l1[0], l1[1]);
-    }
-    __syncthreads();
-    {  // C = Ux' L (16 x 16)
-      double2 cv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
 #pragma unroll
-      for (int k = 0; k < SB; ++k) cv[k & 1] = cadd(cv[k & 1], cmulc(Ux[k][a], L[k][b]));
-      C[a][b] = cadd(cv[0], cv[1]);
+      for (int v = 0; v < 4; ++v) LP[kh][rt * BS + g + 4 * v][m] = make_double2(lr[v], li[v]);
     }
     __syncthreads();
-    stb = C[a][b];
-    sbt = cconj(C[b][a]);
+    {
+      // C = Ux' (LP[0] + LP[1]): wave w takes k-steps 2w, 2w + 1; partial
+      // tiles summed in wave order below
+      double4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int k = (wave * 2 + c) * 4 + g;
+        const double2 u = Ux[k][m], l = cadd(LP[0][k][m], LP[1][k][m]);
+        cr = mma(u.x, l.x, cr);
+        cr = mma(u.y, l.y, cr);
+        ci = mma(u.x, l.y, ci);
+        ci = mma(-u.y, l.x, ci);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) CP[wave][g + 4 * v][m] = make_double2(cr[v], ci[v]);
+    }
+    __syncthreads();
+    stb = cadd(cadd(CP[0][a][b], CP[1][a][b]), cadd(CP[2][a][b], CP[3][a][b]));
+    sbt = cconj(cadd(cadd(CP[0][b][a], CP[1][b][a]), cadd(CP[2][b][a], CP[3][b][a])));
     __syncthreads();  // the LDS is reused below
   }
   // Exchange buffers, double buffered by inner round parity (one barrier
