@@ -68,12 +68,14 @@ COPY_BYTES = 256 << 20
 PATHS_DEFAULT = "fp32,bf16x3,bf16+refine"
 
 
-def summarize_traffic(paths, kernel_prefix):
+def summarize_traffic(paths, kernel_prefix, stride=1, offset=0):
     """HBM bytes per dispatch of one kernel from two rocprofv3 --pmc runs
     (paths = [FETCH_SIZE counter_collection.csv, WRITE_SIZE counter_collection.csv]).
     The plain 256 MiB device copy in the same run (COPY_BYTES read and written,
     the first copy the program dispatches) calibrates each counter;
-    kernel_prefix selects the kernel's dispatches by name."""
+    kernel_prefix selects the kernel's dispatches by name, and of those (in
+    dispatch order) every stride-th from offset (a forward and the line
+    search that shares its shape alternate)."""
     import csv
     vals = {}
     for which, path in zip(("fetch", "write"), paths):
@@ -88,7 +90,8 @@ def summarize_traffic(paths, kernel_prefix):
             if "copy" in name.lower():
                 copy.append((int(r["Dispatch_Id"]), v))
             elif name.startswith(kernel_prefix):
-                dom.append(v)
+                dom.append((int(r["Dispatch_Id"]), v))
+        dom = [v for _, v in sorted(dom)][offset::stride]
         calib = min(copy)[1]  # the 256 MiB calibration copy comes first
         scale = COPY_BYTES / (calib * 1024.0)
         vals[which] = (sum(dom) / len(dom) * 1024.0 * scale, scale, len(dom))
@@ -501,19 +504,24 @@ def main():
                     help="JL filter count x centre-out schedule on the 2-D workload (one JSON line of rows)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="update profiles/traffic.json from two rocprofv3 --pmc runs and exit")
-    ap.add_argument("--tag", default="conv_adj_bf16")
+    ap.add_argument("--tag", default="conv_fwd_bf16")
     ap.add_argument("--prec", default="bf16")
-    ap.add_argument("--kernel", default="void hicu::conv_kernel<1, 1, 8, 1, 2, 1, true, 0>",
+    ap.add_argument("--dispatch-stride", type=int, default=1,
+                    help="counter summary: every stride-th dispatch of the kernel (2 separates a forward from the "
+                         "line search of the same shape)")
+    ap.add_argument("--dispatch-offset", type=int, default=0)
+    ap.add_argument("--kernel", default="void hicu::conv_kernel<1, 1, 8, 2, 4, 1, 1, false, 0>",
                     help="name prefix of the dominant kernel's dispatches in the counter CSV")
     args = ap.parse_args()
     if args.summarize_traffic:
-        vals = summarize_traffic(args.summarize_traffic, args.kernel)
+        vals = summarize_traffic(args.summarize_traffic, args.kernel, args.dispatch_stride, args.dispatch_offset)
         path = os.path.join(ROOT, "profiles", "traffic.json")
         db = json.load(open(path)) if os.path.exists(path) else {}
         db["%s/%s/%s" % (args.workload, args.prec, args.tag)] = dict(
             fetch_bytes_per_launch=vals["fetch"][0], write_bytes_per_launch=vals["write"][0],
             fetch_scale=vals["fetch"][1], write_scale=vals["write"][1], dispatches=vals["fetch"][2],
-            kernel=args.kernel, source_sha=_sha(CONV_SOURCES))
+            kernel=args.kernel, dispatch_stride=args.dispatch_stride, dispatch_offset=args.dispatch_offset,
+            source_sha=_sha(CONV_SOURCES))
         json.dump(db, open(path, "w"), indent=1, sort_keys=True)
         print(json.dumps(db[("%s/%s/%s" % (args.workload, args.prec, args.tag))]))
         return
