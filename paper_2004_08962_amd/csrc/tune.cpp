@@ -29,12 +29,15 @@ std::string key_of(int role, int prec, const Geo& g, int p) {
 // A shape is a candidate when it fits the problem's dimensionality (T0 > 1
 // only with a kernel extent above 1 on axis 0) and, for D > 1, packs
 // outputs of a kernel with at least 3 taps on axis 2; for the batched
-// runtime only shapes with a persistent batched kernel qualify.
+// runtime only shapes with a persistent batched kernel qualify, and not
+// the k-split ones: timed on one slice they won, but over the 64 uneven
+// slices of the batched workload the batched BF16 adjoint with KS = 2 took
+// 0.84 ms against 0.73 ms for 1 x 16 x 16 with two column fragments.
 bool candidate(const Geo& g, int tile, bool batched) {
   const TileCfg t = tile_cfg(tile);
   if (g.k[0] == 1 && g.m[0] <= 1 && t.T0 > 1) return false;
   if (t.D > 1 && g.k[2] < 3) return false;
-  if (batched && !tile_batch_ok(tile)) return false;
+  if (batched && (!tile_batch_ok(tile) || t.KS > 1)) return false;
   return true;
 }
 

@@ -159,7 +159,7 @@ def test_batched_autotune_drives_the_batch(env):
     choice = hb.autotune(_dev(torch, P["x0"]), _dev(torch, np.ascontiguousarray(F)), P["kd"], P["lo"], P["hi"],
                          prec="bf16", batched=True)
     print("batched choice", choice, flush=True)
-    batched_tiles = {0, 1, 2, 3, 4, 5, 9, 13, 14, 15, 36, 37, 41, 42}
+    batched_tiles = {0, 1, 2, 3, 4, 5, 9, 13, 14, 15}  # the tuner skips the batched k-split shapes
     assert choice[0] in batched_tiles and choice[2] in batched_tiles
     b, items = _make_batch(hb, torch, probs, "bf16")
     info = b.info()
