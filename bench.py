@@ -65,7 +65,7 @@ def _traffic(tag, workload, prec):
 
 
 COPY_BYTES = 256 << 20
-PATHS_DEFAULT = "fp32,bf16x3,bf16+refine"
+PATHS_DEFAULT = "fp32,bf16x3,bf16+refine,bf16+refine_x3"
 
 
 def summarize_traffic(paths, kernel_prefix, stride=1, offset=0):
@@ -488,8 +488,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d_256x232x16")
     ap.add_argument("--paths", default=PATHS_DEFAULT,
-                    help="comma list of fp32, bf16x3, bf16+refine, fp16+refine (volumes: fp32, bf16, fp16)")
-    ap.add_argument("--refine", type=int, default=10, help="FP32 steps at the end of the bf16+refine path")
+                    help="comma list of fp32, bf16x3, bf16+refine, bf16+refine_x3, fp16+refine "
+                         "(volumes: fp32, bf16, fp16)")
+    ap.add_argument("--refine", type=int, default=10,
+                    help="steps at the end of a +refine path (FP32; split BF16 for +refine_x3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-routes", action="store_true", help="skip the solve on the other nullspace route")
     ap.add_argument("--route", default="auto", choices=["auto", "gram", "rsvd"],
@@ -580,12 +582,12 @@ def main():
     main_route = args.route if args.route != "auto" else ("rsvd" if args.workload.startswith("cine") else "gram")
     alt_route = "gram" if main_route == "rsvd" else "rsvd"
 
-    def run(prec, refine, route=None):
+    def run(prec, refine, route=None, refine_prec="fp32"):
         route = main_route if route is None else route
         # the 2-D+t study starts from the time-averaged k-space (part of the timed work)
         xs = hicu.time_average_init(x0, mask, axis=0) if P.get("init") == "time_average" else x0
         return hicu.solve(xs, mask, kd, r, sched, p=P["p"], seed=P["seed"], prec=prec, refine_steps=refine, wrap=wrap,
-                          route=route)
+                          route=route, refine_prec=refine_prec)
 
     if args.autotune:
         from paper_2004_08962_amd import batch as hb
@@ -596,19 +598,23 @@ def main():
         del G, Q
     results = {}
     for path in [q.strip() for q in args.paths.split(",") if q.strip()]:
-        prec, refine = (path, 0) if not path.endswith("+refine") else (path.split("+")[0], args.refine)
+        # "<prec>+refine": the last steps in FP32; "<prec>+refine_x3": in split BF16
+        prec, refine, rprec = path, 0, "fp32"
+        if "+" in path:
+            prec, tail = path.split("+")
+            refine, rprec = args.refine, ("bf16x3" if tail == "refine_x3" else "fp32")
         for _ in range(args.warmup):
-            run(prec, refine)
+            run(prec, refine, refine_prec=rprec)
         torch.cuda.synchronize()
         hicu.profile_begin()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            x, trace = run(prec, refine)
+            x, trace = run(prec, refine, refine_prec=rprec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = hicu.profile_end()
         _progress("%s: %.1f ms per solve" % (path, 1e3 * dt / args.steps))
-        results[path] = dict(prec=prec, refine=refine, seconds=dt, ms_per_step=1e3 * dt / args.steps,
+        results[path] = dict(prec=prec, refine=refine, refine_prec=rprec, seconds=dt, ms_per_step=1e3 * dt / args.steps,
                              iters_per_s=args.steps * total_iters / dt, ser=ser(x), prof=prof, x=x.cpu().numpy(),
                              final_J=trace[-1]["J"], sweeps=[t["sweeps"] for t in trace[::sched[0][2]]])
 
@@ -619,12 +625,12 @@ def main():
         rpath = "bf16+refine" if "bf16+refine" in results else next(iter(results))
         rv = results[rpath]
         for _ in range(args.warmup):
-            run(rv["prec"], rv["refine"], alt_route)
+            run(rv["prec"], rv["refine"], alt_route, rv["refine_prec"])
         torch.cuda.synchronize()
         hicu.profile_begin()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            xr, _ = run(rv["prec"], rv["refine"], alt_route)
+            xr, _ = run(rv["prec"], rv["refine"], alt_route, rv["refine_prec"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         rprof = hicu.profile_end()
@@ -663,6 +669,7 @@ def main():
                 config=dict(workload=args.workload, dims=list(P["x0"].shape[:3]), coils=int(P["x0"].shape[3]),
                             kernel=list(kd), rank=r, filters=p, outer=len(sched), inner=sched[0][2],
                             gradient_iters_per_step=total_iters, path=best, refine_steps=b["refine"],
+                            refine_prec=b["refine_prec"] if b["refine"] else None,
                             circular_axes=None if wrap is None else [int(w) for w in wrap], init=P.get("init"),
                             nullspace_route=main_route),
                 pts_filters_per_s=round(b["iters_per_s"] * s_out * p, 1),

@@ -331,12 +331,14 @@ typedef struct {
                                entries of each used as in hicu_geom; NULL = whole array */
   uint64_t seed;            /* JL seed */
   int32_t prec;             /* hicu_prec of the contractions */
-  int32_t refine_steps;     /* the last refine_steps gradient steps of the run use HICU_FP32 */
+  int32_t refine_steps;     /* the last refine_steps gradient steps of the run use refine_prec */
   int32_t warm_start;       /* 1: start each eigensolve from the previous eigenvectors (route 0) */
   int32_t route;            /* nullspace update: 0 = eigendecomposition of the Gram (DISCUSSION),
                                1 = randomized SVD + Householder (THEORY), as hicu_nullspace_rsvd
                                with the sketch of outer iteration i drawn for (seed, i, stream 0) */
   int32_t sketch;           /* route 1: sketch columns l (0 = ceil(3 rank / 2)) */
+  int32_t refine_prec;      /* hicu_prec of the refine steps: HICU_FP32 (0, the default) or
+                               HICU_BF16X3 (split operands on the BF16 matrix cores) */
 } hicu_params;
 
 /* One record per gradient step, filled when trace_host != NULL

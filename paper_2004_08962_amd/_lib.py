@@ -30,7 +30,7 @@ class Params(ctypes.Structure):
     _fields_ = [("rank", c_int32), ("p", c_int32), ("n_outer", c_int32), ("start_outer", c_int32),
                 ("steps", ctypes.POINTER(c_int32)), ("regions", ctypes.POINTER(c_int64)),
                 ("seed", c_uint64), ("prec", c_int32), ("refine_steps", c_int32), ("warm_start", c_int32),
-                ("route", c_int32), ("sketch", c_int32)]
+                ("route", c_int32), ("sketch", c_int32), ("refine_prec", c_int32)]
 
 
 class Trace(ctypes.Structure):

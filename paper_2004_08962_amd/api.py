@@ -280,8 +280,10 @@ def _route(route):
 
 
 def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_steps=0, warm_start=True,
-          start_outer=0, out=None, ws=None, raise_nonfinite=True, wrap=None, route="gram", ell=0):
+          start_outer=0, out=None, ws=None, raise_nonfinite=True, wrap=None, route="gram", ell=0,
+          refine_prec="fp32"):
     """Algorithm 1 on the device.  ``schedule``: list of (lo, hi, steps).
+    The last ``refine_steps`` steps run in ``refine_prec`` ("fp32" or "bf16x3").
     ``route``: nullspace update by the Gram eigendecomposition ("gram") or by
     randomized SVD + Householder ("rsvd", ``ell`` sketch columns, 0 =
     ceil(3 rank / 2)).
@@ -312,6 +314,7 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
     prm.warm_start = 1 if warm_start else 0
     prm.route = _route(route)
     prm.sketch = int(ell)
+    prm.refine_prec = _prec(refine_prec)
     total = sum(int(s[2]) for s in schedule[start_outer:])
     tr = (Trace * max(1, total))()
     x = torch.empty_like(x0) if out is None else out
@@ -331,7 +334,7 @@ def solve(x0, mask, kdims, rank, schedule, p=0, seed=0, prec="fp32", refine_step
 
 
 def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine_steps=0, start_outer=0, wrap=None,
-                          route="gram", ell=0):
+                          route="gram", ell=0, refine_prec="fp32"):
     """Device bytes hicu_solve needs for this problem and schedule."""
     g = geom(shape, kdims, wrap=wrap)
     n_outer = len(schedule)
@@ -343,7 +346,7 @@ def solve_workspace_bytes(shape, kdims, rank, schedule, p=0, prec="fp32", refine
     prm.steps = ctypes.cast(steps, ctypes.POINTER(ctypes.c_int32))
     prm.regions = ctypes.cast(regs, ctypes.POINTER(ctypes.c_int64))
     prm.prec, prm.refine_steps = _prec(prec), int(refine_steps)
-    prm.route, prm.sketch = _route(route), int(ell)
+    prm.route, prm.sketch, prm.refine_prec = _route(route), int(ell), _prec(refine_prec)
     return int(load().hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(prm)))
 
 

@@ -266,6 +266,7 @@ int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* 
   if (!prm || !prm->steps) return HICU_ERR_ARG;
   if (!valid_prec(prm->prec) || prm->n_outer < 0 || prm->start_outer < 0 || prm->refine_steps < 0)
     return HICU_ERR_ARG;
+  if (prm->refine_prec != P_F32 && prm->refine_prec != P_BF16X3) return HICU_ERR_ARG;
   const int n = full.n, r = prm->rank;
   if (r < 0 || r >= n) return HICU_ERR_RANK;
   if (prm->p < 0) return HICU_ERR_RANK;
@@ -295,7 +296,8 @@ int32_t make_solve_plan(const hicu_geom* gm, const hicu_params* prm, SolvePlan* 
   }
   sp->ws_step = sp->ws_gram = sp->ws_rsvd = 0;
   for (int i = prm->start_outer; i < prm->n_outer; ++i) {
-    const size_t a = step_workspace(sp->geos[i], sp->pf, prm->prec), b = step_workspace(sp->geos[i], sp->pf, P_F32);
+    const size_t a = step_workspace(sp->geos[i], sp->pf, prm->prec),
+                 b = step_workspace(sp->geos[i], sp->pf, prm->refine_prec);
     if (a == 0 || b == 0) return HICU_ERR_UNSUPPORTED;
     sp->ws_step = std::max(sp->ws_step, std::max(a, b));
     if (rsvd) {
@@ -392,7 +394,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
     const int64_t step0 = step;
     int prepped_prec = -1;  // precision whose weights of this iteration's F are in the workspace
     for (int j = 0; j < prm->steps[i]; ++j, ++step) {
-      const int prec = (step >= total_steps - prm->refine_steps) ? P_F32 : prm->prec;
+      const int prec = (step >= total_steps - prm->refine_steps) ? prm->refine_prec : prm->prec;
       if (trace) {
         trace[step].outer = i;
         trace[step].inner = j;

@@ -127,6 +127,11 @@ def test_solve_workspace_is_the_callers(lib):
     assert lib.hicu_solve(ctypes.byref(g), fake, None, ctypes.byref(bad), fake, None, fake, b, None) == -3
     badp, keep3 = _params(prec=9)
     assert lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(badp)) == 0
+    # refinement in FP32 (default) or split BF16 only
+    for rp, ok in ((0, True), (2, True), (1, False), (3, False)):
+        q, keep4 = _params(prec=1)
+        q.refine_steps, q.refine_prec = 3, rp
+        assert (lib.hicu_solve_workspace_bytes(ctypes.byref(g), ctypes.byref(q)) > 0) == ok
 
 
 def test_rsvd_workspace_and_validation(lib):

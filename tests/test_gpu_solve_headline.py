@@ -6,8 +6,8 @@ complex64-rounded input in FP64 with an explicit Hankel matrix and dense
 eigh (about half a minute on the host).
 
 Bars: FP32 within 1e-4 relative k-space error of the oracle; the BF16 paths
-(BF16 with 10 FP32 refinement steps, split BF16) within 0.1 dB SER of the
-oracle's."""
+(BF16 with 10 refinement steps in FP32 or in split BF16, split BF16
+throughout) within 0.1 dB SER of the oracle's."""
 import numpy as np
 import pytest
 
@@ -38,11 +38,12 @@ def ref():
     return P, x0, xr, ser, tr
 
 
-def _run(hc, P, x0, prec, refine):
+def _run(hc, P, x0, prec, refine, refine_prec="fp32"):
     import torch
     xd = torch.from_numpy(x0).cuda()
     md = torch.from_numpy(P["mask"]).cuda()
-    x, tr = hc.solve(xd, md, P["kdims"], P["rank"], P["schedule"], prec=prec, refine_steps=refine)
+    x, tr = hc.solve(xd, md, P["kdims"], P["rank"], P["schedule"], prec=prec, refine_steps=refine,
+                     refine_prec=refine_prec)
     return x.cpu().numpy(), tr
 
 
@@ -61,14 +62,17 @@ def test_fp32_matches_oracle(hc, ref):
         assert abs(a["J"] - b["J"]) <= 1e-3 * b["J"], (a, b)
 
 
-@pytest.mark.parametrize("prec,refine", [("bf16", 10), ("bf16x3", 0)], ids=["bf16+refine", "bf16x3"])
-def test_bf16_paths_within_0p1_db(hc, ref, prec, refine):
+@pytest.mark.parametrize("prec,refine,rprec", [("bf16", 10, "fp32"), ("bf16", 10, "bf16x3"), ("bf16x3", 0, "fp32")],
+                         ids=["bf16+refine", "bf16+refine_x3", "bf16x3"])
+def test_bf16_paths_within_0p1_db(hc, ref, prec, refine, rprec):
     P, x0, xr, ser_r, _ = ref
-    xh, tr = _run(hc, P, x0, prec, refine)
+    xh, tr = _run(hc, P, x0, prec, refine, rprec)
     ser = oracle.ser(xh, P["x_true"])
     print("%s: SER %.5f dB, oracle %.5f dB, dSER %.5f, rel err %.3e" % (prec, ser, ser_r, ser - ser_r,
                                                                        oracle.rel_err(xh, xr)), flush=True)
     assert abs(ser - ser_r) <= 0.1
-    assert sum(t["prec"] == 0 for t in tr) == refine
+    code = {"fp32": 0, "bf16x3": 2}[rprec]
+    assert [t["prec"] for t in tr[len(tr) - refine:]] == [code] * refine
+    assert all(t["prec"] == (1 if prec == "bf16" else 2) for t in tr[:len(tr) - refine])
     obs = P["mask"].astype(bool)
     assert np.array_equal(xh[obs], x0[obs])
