@@ -158,7 +158,9 @@ int32_t hicu_set_gram_route(int32_t route);
  * V_dev      optional complex128 n x n, all eigenvectors (columns, same
  *            order and phase rule as Q), usable as the next warm start.
  * sweeps_host optional: number of Jacobi sweeps used.
- * Synchronous on `stream` (the convergence test reads one flag per sweep).
+ * Synchronous on `stream` (the convergence test reads two sums per sweep,
+ * through 32 bytes of pinned host memory that the first call on a host
+ * thread allocates and keeps until the process ends).
  * Returns HICU_ERR_NOCONV if 40 sweeps do not reach relative off-diagonal
  * size 1e-14 (outputs are still written).
  * ------------------------------------------------------------------------ */
@@ -356,8 +358,9 @@ typedef struct {
  * mask_dev  uint8 observed mask (may be NULL).
  * x_out_dev complex64 result; may alias x0_dev.
  * ws_dev    device workspace of at least hicu_solve_workspace_bytes(geom,
- *           params) bytes (0 for invalid arguments); the call allocates
- *           nothing.
+ *           params) bytes (0 for invalid arguments); the call allocates no
+ *           device memory (the eigensolver's 32-byte pinned host slot, see
+ *           hicu_nullspace, is allocated on a thread's first call only).
  * Synchronous (it reads the step scalars once per outer iteration).
  * Non-finite values: an x0 holding NaN/Inf is rejected with
  * HICU_ERR_NONFINITE before anything is written.  If a J, ||g||^2 or eta

@@ -854,10 +854,26 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   // r - 1 (A[cur] -> A[cur ^ 1]) while solving round r, then the last apply.
   auto par = [](int r) { return (r + 2) & 1; };
   int cur = 0;
-  for (;;) {
+  // Each sweep's convergence sums reach the host through pinned memory of
+  // this host thread while the GPU already runs the next sweep's opening
+  // round, which writes only the round buffers (no effect on A or V when
+  // the host then stops).
+  static thread_local double* h_sums = nullptr;
+  if (!h_sums) HICU_HIP_TRY(hipHostMalloc((void**)&h_sums, 4 * sizeof(double), hipHostMallocDefault));
+  struct Event {
+    hipEvent_t e = nullptr;
+    ~Event() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } done;
+  HICU_HIP_TRY(hipEventCreateWithFlags(&done.e, hipEventDisableTiming));
+  auto opening = [&]() {
     // opening round: blocks (2 j, 2 j + 1) with all their index pairs
     hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)Abuf[cur], np, nb, -1,
                        tol_inner, (const double*)dfloor, Ubuf[par(-1)], idbuf[par(-1)], Sbuf[par(-1)]);
+  };
+  opening();
+  for (;;) {
     for (int r = 0; r <= nb - 1; ++r) {
       const bool last = r == nb - 1;  // apply only
       const int npr = last ? 0 : npair;
@@ -870,8 +886,13 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
     hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nwg, dsums);
     HICU_HIP_TRY(hipGetLastError());
     ++sweeps;
-    HICU_HIP_TRY(hipMemcpyAsync(sums, dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HICU_HIP_TRY(hipStreamSynchronize(st));
+    HICU_HIP_TRY(hipMemcpyAsync(h_sums, dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HICU_HIP_TRY(hipEventRecord(done.e, st));
+    opening();  // the next sweep's, on the chance that this one has not converged
+    HICU_HIP_TRY(hipGetLastError());
+    HICU_HIP_TRY(hipEventSynchronize(done.e));
+    sums[0] = h_sums[0];
+    sums[1] = h_sums[1];
     const double rel = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : 0.0;
     if (!(rel == rel) || !std::isfinite(sums[1])) {
       status = HICU_ERR_NONFINITE;
