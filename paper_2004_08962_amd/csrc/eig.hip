@@ -281,8 +281,9 @@ constexpr size_t kRoundLds = 56 * 1024;
 // and thread column t only; between inner rounds s advances by one and the
 // Q parts move one thread row / column through LDS.  Thread (a, b) also
 // holds U[i][P a] and U[i][Q s(a)] for rows i = b, b + 16, so it needs
-// rotations a and b only, which it forms itself from the published
-// diagonal blocks (one barrier per inner round).  Outputs: U (unless no
+// rotations a and b only: it forms rotation b from the published diagonal
+// blocks and reads rotation a from a lane of its wave (one barrier per
+// inner round).  Outputs: U (unless no
 // rotation was needed), the identity flag, and the final diagonal
 // 16-blocks for the next round.
 __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair, const double2* Ucur,
@@ -404,9 +405,10 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     d0c[a] = stb;
   }
   __syncthreads();
-  // rotation inputs of indices a and b (diagonal 2x2 blocks of round 0)
-  double aa = d0a[a], ba = d0b[a], ab = d0a[b], bb = d0b[b];
-  double2 ca = d0c[a], cb = d0c[b];
+  // rotation inputs of index b (diagonal 2x2 block of round 0)
+  const double aa = d0a[a];
+  double ab = d0a[b], bb = d0b[b];
+  double2 cb = d0c[b];
   {
     // early exit when no cross entry is above the rotation thresholds
     const double v2 = stb.x * stb.x + stb.y * stb.y;
@@ -427,11 +429,18 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
   int nrot = 0;
   const int a1 = (a + 1) & 15, b1 = (b + 1) & 15;
   for (int k = 0; k < BS; ++k) {
-    // every thread forms the two rotations it uses (identical arithmetic
-    // on identical inputs in every thread)
+    // Each lane forms rotation b (its column index) and takes rotation a
+    // from the lane of its row group whose column index is a: every wave
+    // holds all 16 columns, so no rotation is formed more than four times.
     Rot ra, rb;
-    const bool did = make_rot_fast(aa, ba, ca, tol, fl, &ra);
-    make_rot_fast(ab, bb, cb, tol, fl, &rb);
+    const bool did = make_rot_fast(ab, bb, cb, tol, fl, &rb);
+    {
+      const int src = (tid & 63 & ~15) | a;
+      ra.cs = __shfl(rb.cs, src);
+      ra.sn = __shfl(rb.sn, src);
+      ra.e.x = __shfl(rb.e.x, src);
+      ra.e.y = __shfl(rb.e.y, src);
+    }
     if (a == b) nrot += did;
     rot2x2(ra, rb, stt, stb, sbt, sbb);
     if (a == b && did) {
@@ -463,9 +472,6 @@ __device__ void pair_role(const double2* Ain, int npad, int nb, int r, int pair,
     ub[1] = xu(pb, 1)[a1][b];
     // diagonal block of index t after the shift: P-P entry unchanged,
     // P-Q entry from block (t, t + 1), Q-Q entry from block (t + 1, t + 1)
-    aa = xd(pb)[a];
-    ca = xtb(pb)[a][a1];
-    ba = xbb(pb)[a1][a1].x;
     ab = xd(pb)[b];
     cb = xtb(pb)[b][b1];
     bb = xbb(pb)[b1][b1].x;
