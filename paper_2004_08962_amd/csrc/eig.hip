@@ -8,13 +8,17 @@
 // every pair of blocks once (round-robin "circle" schedule, nb - 1 rounds of
 // nb/2 disjoint pairs) rotating only the 256 index pairs across the two
 // blocks (16 inner rounds instead of 31): each index pair is rotated once
-// per sweep.  In each round one workgroup per pair works on its subproblem
-// with complex Jacobi rotations in LDS, and a second kernel applies the
-// block-diagonal unitary W to the whole matrix and to the eigenvector
-// accumulator (A <- W' A W, V <- V W) one 32 x 32 block per workgroup, in
-// place.  Pairs that are already diagonal are skipped, so
-// warm-started solves (the previous eigenvectors as V0) cost little.  A sweep
-// ends with a relative off-diagonal test; FP64 throughout.
+// per sweep.  The opening round's subproblems are solved in LDS by
+// pair_eig_kernel.  Each later round is one round_kernel launch: its first
+// workgroups solve that round's subproblems (blocks formed from the
+// previous round's results, rotations with the subproblem in registers)
+// while the others apply the previous round's block-diagonal unitary W to
+// the matrix and to the eigenvector accumulator (A <- W' A W into the
+// other of two buffers, V <- V W in place) on the FP64 matrix cores.
+// Pairs whose subproblem needs no rotation are flagged and their update is
+// a copy, so warm-started solves (the previous eigenvectors as V0) cost
+// little.  A sweep ends with a relative off-diagonal test; FP64
+// throughout.
 #include <algorithm>
 #include <cmath>
 #include <vector>
