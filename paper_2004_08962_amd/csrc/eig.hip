@@ -3,12 +3,11 @@
 // DISCUSSION section).
 //
 // The matrix is split into 16-wide index blocks.  A sweep opens with one
-// round over the block pairs (2j, 2j + 1) that rotates every index pair of
-// each 32 x 32 subproblem (so every in-block pair is visited), then visits
-// every pair of blocks once (round-robin "circle" schedule, nb - 1 rounds of
-// nb/2 disjoint pairs) rotating only the 256 index pairs across the two
-// blocks (16 inner rounds instead of 31): each index pair is rotated once
-// per sweep.  The opening round's subproblems are solved in LDS by
+// round over the block pairs (2j, 2j + 1) that rotates the index pairs
+// inside each block (so every in-block pair is visited), then visits every
+// pair of blocks once (round-robin "circle" schedule, nb - 1 rounds of nb/2
+// disjoint pairs) rotating the 256 index pairs across the two blocks: each
+// index pair is rotated once per sweep.  The opening round's subproblems are solved in LDS by
 // pair_eig_kernel.  Each later round is one round_kernel launch: its first
 // workgroups solve that round's subproblems (blocks formed from the
 // previous round's results, rotations with the subproblem in registers)
@@ -120,7 +119,8 @@ __device__ __forceinline__ bool make_rot_fast(double a, double b, double2 c, dou
 }
 
 // One workgroup (1024 threads) per block pair: cyclic Jacobi on the 32x32
-// subproblem in LDS, U written to Ubuf[pair].  Each inner round: 16 lanes
+// subproblem in LDS, U written to Ubuf[pair]; the opening round rotates
+// the in-block pairs of both blocks (15 inner rounds).  Each inner round: 16 lanes
 // compute the 16 rotations (skipping entries below the relative tolerance or
 // the absolute noise floor), then every thread produces one element of the
 // rotated S (double buffered) and one element of U.  Sfin[pair] receives
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
     const int i = tid >> 5, j = tid & 31;
     const double2 v = S[0][i][j];
     const double v2 = v.x * v.x + v.y * v.y;
-    const bool active = cross ? ((i < BS) != (j < BS)) : i != j;
+    const bool active = cross ? ((i < BS) != (j < BS)) : ((i < BS) == (j < BS) && i != j);
     const bool big = active && v2 > fl * fl && v2 > tol * tol * fabs(S[0][i][i].x * S[0][j][j].x);
     if (tid == 0) nrot_round = 0;
     __syncthreads();
@@ -170,14 +170,16 @@ __global__ __launch_bounds__(1024) void pair_eig_kernel(const double2* A, int np
   const int ut = tid - 256, ui = ut >> 4, ub = ut & 15;
   int cur = 0, total = 0;
   for (int sweep = 0; sweep < MAX_INNER; ++sweep) {
-    for (int r = 0; r < (cross ? BS : SB - 1); ++r) {
+    for (int r = 0; r < (cross ? BS : BS - 1); ++r) {
       __syncthreads();
       if (tid < SB / 2) {
-        // opening round: every pair of the 32 indices (circle schedule);
-        // later rounds: only the pairs across the two blocks, whose
-        // in-block pairs the opening round has rotated
-        const int p = cross ? tid : circle_pos(tid, r, SB);
-        const int q = cross ? BS + (tid + r) % BS : circle_pos(SB - 1 - tid, r, SB);
+        // opening round: the pairs inside each of the two blocks (a circle
+        // schedule on 16 indices per block, 8 rotations each); the pairs
+        // across two blocks are rotated in the circle round that pairs
+        // those blocks (cross rounds: t with BS + (t + r) mod BS)
+        const int blk = tid >> 3, tt = tid & 7;
+        const int p = cross ? tid : blk * BS + circle_pos(tt, r, BS);
+        const int q = cross ? BS + (tid + r) % BS : blk * BS + circle_pos(BS - 1 - tt, r, BS);
         Rot ro;
         const bool did = make_rot_fast(S[cur][p][p].x, S[cur][q][q].x, S[cur][p][q], tol, fl, &ro);
         ro.p = p;
