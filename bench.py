@@ -606,7 +606,10 @@ def main():
         for _ in range(args.warmup):
             run(prec, refine, refine_prec=rprec)
         torch.cuda.synchronize()
-        hicu.profile_begin()
+        # events on the contractions, Gram, eigensolver and rSVD/JL steps only:
+        # the per-step scalar kernels stay untimed (each event record costs
+        # a few us, 4 % of the solve when every launch is bracketed)
+        hicu.profile_begin(minor=False)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             x, trace = run(prec, refine, refine_prec=rprec)
@@ -627,7 +630,7 @@ def main():
         for _ in range(args.warmup):
             run(rv["prec"], rv["refine"], alt_route, rv["refine_prec"])
         torch.cuda.synchronize()
-        hicu.profile_begin()
+        hicu.profile_begin(minor=False)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             xr, _ = run(rv["prec"], rv["refine"], alt_route, rv["refine_prec"])

@@ -485,6 +485,11 @@ int32_t hicu_tile_info(int32_t tile, int32_t* cfg);
  * 8 n p s real flops each: one complex multiply-add per tap, filter and
  * output; the Gram 4 s n^2, the count of a Hermitian product H'H).
  * Process-wide; not meant for concurrent use from several threads.
+ * hicu_profile_begin_major() times only the contractions, the Gram, the
+ * eigensolver, the rSVD and JL steps and the batched launches: the per-step
+ * scalar and layout kernels (reductions, line-search step, update, weight
+ * layouts, scaling) go untimed, which keeps the events' own cost (a few us
+ * per record) out of a timed run.
  * ------------------------------------------------------------------------ */
 typedef struct {
   char name[24];
@@ -494,6 +499,7 @@ typedef struct {
 } hicu_kernel_stat;
 
 int32_t hicu_profile_begin(void);
+int32_t hicu_profile_begin_major(void);
 int32_t hicu_profile_end(hicu_kernel_stat* stats, int32_t max_stats, int32_t* n_stats);
 
 #ifdef __cplusplus

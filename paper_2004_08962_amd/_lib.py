@@ -88,6 +88,7 @@ SIGNATURES = {
     "hicu_line_search_noalloc": (c_int32, [ctypes.POINTER(Geom), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                            c_void_p, c_void_p]),
     "hicu_profile_begin": (c_int32, []),
+    "hicu_profile_begin_major": (c_int32, []),
     "hicu_profile_end": (c_int32, [ctypes.POINTER(KernelStat), c_int32, ctypes.POINTER(c_int32)]),
     "hicu_batch_create": (c_int32, [ctypes.POINTER(BatchItem), c_int32, c_int32, ctypes.POINTER(c_void_p),
                                     ctypes.POINTER(c_size_t)]),

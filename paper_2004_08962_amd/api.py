@@ -367,9 +367,13 @@ def time_average_init(x0, mask, axis=0, out=None):
     return out
 
 
-def profile_begin():
-    """Start per-kernel event timing (every library launch, on its stream)."""
-    check(load().hicu_profile_begin(), "hicu_profile_begin")
+def profile_begin(minor=True):
+    """Start per-kernel event timing (every library launch, on its stream);
+    minor=False leaves the per-step scalar and layout kernels untimed."""
+    if minor:
+        check(load().hicu_profile_begin(), "hicu_profile_begin")
+    else:
+        check(load().hicu_profile_begin_major(), "hicu_profile_begin_major")
 
 
 def profile_end(max_stats=64):

@@ -240,7 +240,7 @@ int32_t hicu_update(const hicu_geom* gm, void* x, const void* gv, const double* 
   Geo g;
   HICU_TRY(make_geo(gm, &g));
   if (!x || !gv || !eta) return HICU_ERR_ARG;
-  ProfScope ps("update", (hipStream_t)stream, 0.0, 24.0 * (double)g.npts * g.nc);
+  ProfScope ps("update", (hipStream_t)stream, 0.0, 24.0 * (double)g.npts * g.nc, true);
   return launch_update(reinterpret_cast<float2*>(x), reinterpret_cast<const float2*>(gv), eta,
                        g.npts * g.nc, (hipStream_t)stream);
 }
@@ -416,7 +416,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
       double* Jd = sc + 3 * step;
       HICU_TRY(objective_grad_impl(gi, x, mask, F, pf, prec, Jd, g, Jd + 1, at(ws, pl.o_step), pl.ws_step, st, prep));
       HICU_TRY(line_search_impl(gi, g, Jd + 1, F, pf, prec, Jd + 2, at(ws, pl.o_step), pl.ws_step, st, true));
-      ProfScope ps("update", st, 0.0, 24.0 * (double)N);
+      ProfScope ps("update", st, 0.0, 24.0 * (double)N, true);
       HICU_TRY(launch_update(x, g, Jd + 2, (int64_t)N, st));
     }
     // The step scalars of this iteration: a non-finite J or gradient stops the

@@ -381,7 +381,7 @@ int32_t batch_step(hicu_batch_s* b, hipStream_t st) {
                        (const uint32_t*)counter);
   }
   {
-    ProfScope ps("prep_weights", st);
+    ProfScope ps("prep_weights", st, 0.0, 0.0, true);
     HICU_TRY(launch_prep_weights_batch(reinterpret_cast<const PrepArgs*>(at(ws, b->t_prep_f)), count, b->max_prep_f,
                                        st));
     HICU_TRY(launch_prep_weights_batch(reinterpret_cast<const PrepArgs*>(at(ws, b->t_prep_a)), count, b->max_prep_a,

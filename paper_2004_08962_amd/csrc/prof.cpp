@@ -18,6 +18,7 @@ struct Rec {
 
 std::mutex mu;
 bool enabled = false;
+bool major_only = false;
 thread_local int suppressed = 0;
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
@@ -28,8 +29,10 @@ hipEvent_t get_event() {
     pool.pop_back();
     return e;
   }
+  // Timing only: no system-scope fence when the event completes (the host
+  // reads nothing through these events), which keeps each record cheap.
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -43,11 +46,11 @@ bool prof_on() {
   return enabled;
 }
 
-ProfScope::ProfScope(const char* tag, hipStream_t st, double flops, double bytes)
+ProfScope::ProfScope(const char* tag, hipStream_t st, double flops, double bytes, bool minor)
     : tag_(tag), st_(st), flops_(flops), bytes_(bytes) {
   if (suppressed) return;
   std::lock_guard<std::mutex> l(mu);
-  if (!enabled) return;
+  if (!enabled || (minor && major_only)) return;
   a_ = get_event();
   if (a_ && hipEventRecord(a_, st_) != hipSuccess) {
     pool.push_back(a_);
@@ -73,7 +76,7 @@ using namespace hicu;
 
 extern "C" {
 
-int32_t hicu_profile_begin(void) {
+static int32_t profile_start(bool major) {
   std::lock_guard<std::mutex> l(mu);
   for (auto& r : recs) {
     pool.push_back(r.a);
@@ -81,8 +84,13 @@ int32_t hicu_profile_begin(void) {
   }
   recs.clear();
   enabled = true;
+  major_only = major;
   return HICU_OK;
 }
+
+int32_t hicu_profile_begin(void) { return profile_start(false); }
+
+int32_t hicu_profile_begin_major(void) { return profile_start(true); }
 
 int32_t hicu_profile_end(hicu_kernel_stat* out, int32_t max_out, int32_t* n_out) {
   std::lock_guard<std::mutex> l(mu);

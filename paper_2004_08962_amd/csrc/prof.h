@@ -19,10 +19,11 @@ class ProfSuppress {
 
 // Records a start event at construction and a stop event at destruction on
 // `st` when profiling is enabled; `flops`/`bytes` are the algorithmic work of
-// the bracketed launch.
+// the bracketed launch.  `minor` marks the per-step scalar and layout
+// kernels, which a major-only profile leaves untimed.
 class ProfScope {
  public:
-  ProfScope(const char* tag, hipStream_t st, double flops = 0.0, double bytes = 0.0);
+  ProfScope(const char* tag, hipStream_t st, double flops = 0.0, double bytes = 0.0, bool minor = false);
   ~ProfScope();
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;

@@ -227,7 +227,7 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   const float2* Fc = reinterpret_cast<const float2*>(F);
   const double nS = (double)region_points(g);
   if (prep & kPrepForward) {
-    ProfScope ps("prep_weights", st);
+    ProfScope ps("prep_weights", st, 0.0, 0.0, true);
     HICU_TRY(launch_prep_weights(0, prec, g, Fc, p, sp.wf, at(ws, sp.off_Bf), at(ws, sp.off_Bflo), st));
   }
   float2* Y = reinterpret_cast<float2*>(at(ws, sp.off_Y));
@@ -239,17 +239,17 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
   float* scales = reinterpret_cast<float*>(at(ws, sp.off_sc));
   float* pmax = reinterpret_cast<float*>(at(ws, sp.off_pmax));
   if (f16) {
-    ProfScope ps("scale", st);
+    ProfScope ps("scale", st, 0.0, 0.0, true);
     HICU_TRY(launch_absmax(reinterpret_cast<const float*>(x), 2 * g.npts * g.nc, pmax, st));
     HICU_TRY(launch_scale(pmax, kAbsmaxBlocks, scales, st));
   }
   if (gout) {
     if (!full_region(g)) {
-      ProfScope ps("zero", st);
+      ProfScope ps("zero", st, 0.0, 0.0, true);
       HICU_TRY(launch_zero(gout, (size_t)g.npts * g.nc * sizeof(float2), st));
     }
     if (prep & kPrepAdjoint) {
-      ProfScope ps("prep_weights", st);
+      ProfScope ps("prep_weights", st, 0.0, 0.0, true);
       HICU_TRY(launch_prep_weights(1, prec, g, Fc, p, sp.wa, at(ws, sp.off_Ba), at(ws, sp.off_Balo), st));
     }
   }
@@ -304,7 +304,7 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
       ca.a.is[2] = sp.ybw;
     }
     if (f16) {
-      ProfScope ps("scale", st);
+      ProfScope ps("scale", st, 0.0, 0.0, true);
       HICU_TRY(launch_scale(pmax + pmax0, cf.gx * cf.gy, scales + 1, st));
       ca.a.in_scale = scales + 1;
     }
@@ -314,11 +314,11 @@ int32_t objective_grad_impl(const Geo& g, const void* x, const uint8_t* mask, co
     }
   }
   if (J) {
-    ProfScope ps("reduce", st);
+    ProfScope ps("reduce", st, 0.0, 0.0, true);
     HICU_TRY(launch_reduce(pf, pf_used, J, st));
   }
   if (gout && gn2) {
-    ProfScope ps("reduce", st);
+    ProfScope ps("reduce", st, 0.0, 0.0, true);
     HICU_TRY(launch_reduce(pa, sp.na_blocks, gn2, st));
   }
   return HICU_OK;
@@ -352,14 +352,14 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
   }
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
   if (!grad_weights) {
-    ProfScope ps("prep_weights", st);
+    ProfScope ps("prep_weights", st, 0.0, 0.0, true);
     HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
                                  at(ws, sp.off_Bflo), st));
   }
   double* pz = reinterpret_cast<double*>(at(ws, sp.off_pz));
   fill_forward_args(g, gv, sp, ws, nullptr, pz);
   if (prec == P_F16) {
-    ProfScope ps("scale", st);
+    ProfScope ps("scale", st, 0.0, 0.0, true);
     float* scales = reinterpret_cast<float*>(at(ws, sp.off_sc));
     float* pmax = reinterpret_cast<float*>(at(ws, sp.off_pmax));
     HICU_TRY(launch_absmax(reinterpret_cast<const float*>(gv), 2 * g.npts * g.nc, pmax, st));
@@ -371,7 +371,7 @@ int32_t line_search_impl(const Geo& g, const void* gv, const double* gn2, const 
     HICU_TRY(launch_conv(sp.cf, st));
   }
   {
-    ProfScope ps("eta", st);
+    ProfScope ps("eta", st, 0.0, 0.0, true);
     HICU_TRY(launch_eta(pz, sp.nf_blocks, gn2, eta, st));
   }
   return HICU_OK;
@@ -402,7 +402,7 @@ int32_t forward_store_impl(const Geo& g, const void* x, const void* F, int p, in
   HICU_TRY(make_step_plan(g, p, prec, false, &sp));
   if (!ws || ws_bytes < sp.total) return HICU_ERR_WORKSPACE;
   {
-    ProfScope ps("prep_weights", st);
+    ProfScope ps("prep_weights", st, 0.0, 0.0, true);
     HICU_TRY(launch_prep_weights(0, prec, g, reinterpret_cast<const float2*>(F), p, sp.wf, at(ws, sp.off_Bf),
                                  at(ws, sp.off_Bflo), st));
   }
