@@ -33,9 +33,6 @@ constexpr int MAX_INNER = 1;  // inner sweeps per subproblem (the outer sweeps f
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csc(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
@@ -83,17 +80,13 @@ __device__ __forceinline__ void block_indices(int r, int nb, int pair, int* idx)
   }
 }
 
-// Fast unitary-to-rounding rotation: reciprocal square roots and
-// reciprocals from the hardware approximations plus one Newton step each.
+// Fast unitary-to-rounding rotation: reciprocal square roots from the
+// hardware approximation (about 2^-24 relative) plus two Newton steps
+// (2^-52; one step leaves 2^-48).
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
   return y * (1.5 - 0.5 * x * y * y);
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * (2.0 - x * y);
-  return y * (2.0 - x * y);
 }
 
 // With d = (b - a) / 2 and r = sqrt(d^2 + |c|^2): cos^2 = (1 + |d| / r) / 2,
