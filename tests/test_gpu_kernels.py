@@ -218,3 +218,24 @@ def test_jl_draw_matches_oracle(hc):
     np.testing.assert_allclose(_host(Pm), Pr, rtol=1e-13, atol=1e-13)
     Fr = Q.astype(np.complex128) @ Pr
     np.testing.assert_allclose(_host(F), Fr, rtol=0, atol=1e-5 * np.abs(Fr).max())
+
+
+def test_profile_major_only(hc):
+    """Major-only event timing records the contractions but not the
+    per-step scalar kernels; full timing records both."""
+    import torch
+    x, mask = _rand_problem((1, 24, 24, 2), (1, 3, 3), seed=31)
+    kd = (1, 3, 3)
+    n = 18
+    rng = np.random.default_rng(32)
+    F = ((rng.standard_normal((n, 6)) + 1j * rng.standard_normal((n, 6))) / np.sqrt(n)).astype(np.complex64)
+    xd, md, Fd = _dev(x), _dev(mask), _dev(F)
+    for minor in (False, True):
+        hc.profile_begin(minor=minor)
+        J, g, gn2 = hc.objective_grad(xd, md, Fd, kd, prec="fp32")
+        hc.line_search(g, gn2, Fd, kd, prec="fp32")
+        torch.cuda.synchronize()
+        prof = hc.profile_end()
+        print("minor", minor, sorted(prof), flush=True)
+        assert {"conv_fwd_fp32", "conv_adj_fp32", "conv_els_fp32"} <= set(prof)
+        assert ("reduce" in prof) == minor and ("eta" in prof) == minor
