@@ -37,6 +37,7 @@ namespace hicu {
 
 // Positions (steps of 4) fetched ahead of the MFMAs that use them.
 constexpr int kGramAhead = 8;
+constexpr int kCorrAhead = 6;
 
 struct GramArgs {
   const float* x;       // complex64 array viewed as floats
@@ -322,14 +323,21 @@ __host__ __device__ inline int corr_groups(int nd_half, int T) { return (nd_half
 // real-embedding tiles of sum_w x[w] x[w + d]^T with v_mfma_f64_16x16x4
 // (4 points per step; lane group g takes points g, g + 4, ...).  x[w + d]
 // outside the region counts as zero (such cell/shift pairs are never
-// assembled); on a circular axis it wraps.  Operands are fetched kGramAhead
+// assembled); on a circular axis it wraps.  Operands are fetched kCorrAhead
 // steps ahead and widened to FP64 at use.
 template <int T>
 __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   constexpr int DW = corr_dw(T);
   const int ngrp = corr_groups(a.nd_half, T);
-  const int64_t lin = gram_remap(blockIdx.x, (int64_t)a.nent * ngrp);
-  const int ent = (int)(lin / ngrp), grp = (int)(lin % ngrp);
+  // Workgroups are dealt to the 8 XCDs in turn.  Entry e runs on XCD
+  // e mod 8 with all its shift groups there back to back: neighbouring
+  // entries have similar sizes, so every XCD gets an even share of the
+  // heavy core entries, and the groups of one entry share an L2.  (Giving
+  // each XCD a contiguous range of entries instead put the whole core cell
+  // on one or two XCDs.)
+  const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+  const int ent = (int)((idx / ngrp) * 8 + xcd), grp = (int)(idx % ngrp);
+  if (ent >= a.nent) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, m = lane & 15;
   const int h0 = (grp * 4 + wave) * DW;
   if (h0 >= a.nd_half) return;
@@ -382,42 +390,58 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   int64_t p2 = q % cln[2], p1 = (q / cln[2]) % cln[1], p0 = q / (cln[2] * cln[1]);
   auto base_of = [&]() { return (((cst[0] + p0) * a.d1 + (cst[1] + p1)) * a.d2 + (cst[2] + p2)) * two_nc; };
   int64_t base = base_of();
+  // A lane past the entry's end reads at the entry's first point instead
+  // (in the region, and so is each of its in-region shifts); masked-off
+  // components read component 0.  Loads carry no select: the masks are
+  // applied where the values are used, so the compiler never has to wait
+  // for a load before the ring moves on.
+  const int64_t base_first = (((cst[0] + q_begin / (cln[2] * cln[1])) * a.d1 + (cst[1] + (q_begin / cln[2]) % cln[1])) *
+                                  a.d2 + (cst[2] + q_begin % cln[2])) * two_nc;
+  int offc[T];
+#pragma unroll
+  for (int i = 0; i < T; ++i) offc[i] = okc[i] ? 16 * i + m : 0;
+  // Shifts out of the region read the unshifted point (their values are
+  // masked to zero).  The empty asm hides that from the optimiser, which
+  // would otherwise reuse the unshifted load for such shifts and so wait
+  // for that load in the step that issues it.
+  int64_t soff[DW];
+#pragma unroll
+  for (int u = 0; u < DW; ++u) {
+    soff[u] = inb[u] ? doff[u] : 0;
+    asm volatile("" : "+v"(soff[u]));
+  }
   auto wrap_to = [](int64_t v, int64_t P) { return P == 0 ? v : (v < 0 ? v + P : (v >= P ? v - P : v)); };
   // The two paths get separate loops, so the fast one carries no wrap or
-  // bound logic.  Fast loads always issue (a masked-off lane reads element
-  // 0 and its value is replaced by zero), which keeps them unpredicated.
+  // bound logic.  The slow path keeps a per-slot bit mask (bit u: shift u's
+  // point lies in the region).
   auto run = [&](auto fast_tag) {
     constexpr bool FAST = decltype(fast_tag)::value;
-    auto fetch = [&](float (&av)[T], float (&bv)[DW][T]) {
+    auto fetch = [&](float (&av)[T], float (&bv)[DW][T], unsigned& mk) {
       const bool ok = q < q_end;
       if constexpr (FAST) {
+        const int64_t b = ok ? base : base_first;
 #pragma unroll
-        for (int i = 0; i < T; ++i) {
-          const bool on = ok && okc[i];
-          const float v = a.x[on ? base + 16 * i + m : 0];
-          av[i] = on ? v : 0.f;
-        }
+        for (int i = 0; i < T; ++i) av[i] = a.x[b + offc[i]];
 #pragma unroll
         for (int u = 0; u < DW; ++u)
 #pragma unroll
-          for (int i = 0; i < T; ++i) {
-            const bool on = ok && inb[u] && okc[i];
-            const float v = a.x[on ? base + doff[u] + 16 * i + m : 0];
-            bv[u][i] = on ? v : 0.f;
-          }
+          for (int i = 0; i < T; ++i) bv[u][i] = a.x[b + soff[u] + offc[i]];
+        mk = 0;
       } else {
 #pragma unroll
-        for (int i = 0; i < T; ++i) av[i] = (ok && okc[i]) ? a.x[base + 16 * i + m] : 0.f;
+        for (int i = 0; i < T; ++i) av[i] = a.x[(ok ? base : base_first) + offc[i]];
         const int64_t w0 = cst[0] + p0, w1 = cst[1] + p1, w2 = cst[2] + p2;
+        mk = 0;
 #pragma unroll
         for (int u = 0; u < DW; ++u) {
           const int64_t v0 = wrap_to(w0 + d[u][0], a.per[0]), v1 = wrap_to(w1 + d[u][1], a.per[1]),
                         v2 = wrap_to(w2 + d[u][2], a.per[2]);
           const bool okb = ok && hok[u] && v0 >= a.lo[0] && v0 < a.hi[0] && v1 >= a.lo[1] && v1 < a.hi[1] &&
                            v2 >= a.lo[2] && v2 < a.hi[2];
-          const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : 0;
+          const int64_t bbase = okb ? ((v0 * a.d1 + v1) * a.d2 + v2) * two_nc : base_first;
+          mk |= okb ? 1u << u : 0u;
 #pragma unroll
-          for (int i = 0; i < T; ++i) bv[u][i] = (okb && okc[i]) ? a.x[bbase + 16 * i + m] : 0.f;
+          for (int i = 0; i < T; ++i) bv[u][i] = a.x[bbase + offc[i]];
         }
       }
       q += 4;
@@ -435,29 +459,36 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
         base = base_of();
       }
     };
-    constexpr int PF = kGramAhead;
+    constexpr int PF = kCorrAhead;
     float av[PF][T], bv[PF][DW][T];
+    unsigned mk[PF];
 #pragma unroll
-    for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+    for (int r = 0; r < PF; ++r) fetch(av[r], bv[r], mk[r]);
+    // Whole blocks of PF steps: steps past the entry's end see all-zero
+    // operands (their lanes are masked), which keeps the block free of
+    // exits.
     for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
 #pragma unroll
       for (int r = 0; r < PF; ++r) {
-        if (q0 + 4 * r >= q_end) break;
+        // masks as factors 1 or 0: a select on a loaded value would make
+        // the compiler wait for (or predicate) the load where it is issued
+        const bool ok = q0 + 4 * r + g < q_end;
         double ad[T];
 #pragma unroll
-        for (int i = 0; i < T; ++i) ad[i] = (double)av[r][i];
+        for (int i = 0; i < T; ++i) ad[i] = (double)(av[r][i] * (ok && okc[i] ? 1.f : 0.f));
 #pragma unroll
         for (int u = 0; u < DW; ++u) {
+          const bool okb = FAST ? ok && inb[u] : ((mk[r] >> u) & 1u) != 0;
           double bd[T];
 #pragma unroll
-          for (int j = 0; j < T; ++j) bd[j] = (double)bv[r][u][j];
+          for (int j = 0; j < T; ++j) bd[j] = (double)(bv[r][u][j] * (okb && okc[j] ? 1.f : 0.f));
 #pragma unroll
           for (int i = 0; i < T; ++i)
 #pragma unroll
             for (int j = 0; j < T; ++j)
               acc[u][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[i], bd[j], acc[u][i][j], 0, 0, 0);
         }
-        fetch(av[r], bv[r]);  // the step PF positions further on
+        fetch(av[r], bv[r], mk[r]);  // the step PF positions further on
       }
     }
   };
@@ -647,7 +678,7 @@ static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, s
     a.cellsum = reinterpret_cast<double*>(b + cp.off_cellsum);
     hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(64), 0, st, a);
     const int ngrp = corr_groups(a.nd_half, cp.T);
-    const dim3 grid((unsigned)((int64_t)a.nent * ngrp));
+    const dim3 grid((unsigned)(rup((int64_t)a.nent, 8) * ngrp));
     switch (cp.T) {
       case 1: hipLaunchKernelGGL(corr_kernel<1>, grid, dim3(256), 0, st, a); break;
       case 2: hipLaunchKernelGGL(corr_kernel<2>, grid, dim3(256), 0, st, a); break;
