@@ -139,30 +139,27 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
   int64_t xbase = xbase_of(), ybase = q * two_l;
   auto run = [&](auto wrap_tag) {
     constexpr bool WRAP = decltype(wrap_tag)::value;
+    // Loads carry no select: lanes that are off read element 0 and the
+    // masks are applied where the values are used (a select right after
+    // a load makes the compiler wait for it where it is issued).
     auto fetch = [&](float (&av)[2], float (&bv)[2]) {
       const bool ok = q < q_end;
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
+        const bool on = ok && on_[f];
         if constexpr (!WRAP) {
-          // the load always issues (a masked-off lane reads element 0)
-          const bool on = ok && on_[f];
-          const float v = src[f][on ? (ax_[f] ? xbase : ybase) + aoff[f] : 0];
-          av[f] = on ? v : 0.f;
+          av[f] = src[f][on ? (ax_[f] ? xbase : ybase) + aoff[f] : 0];
         } else {
-          float v = 0.f;
-          if (ok && ra[f].kind == 0) {
-            const int64_t i0 = wrapped(a.lo[0] + u0 + ra[f].k0, a.per[0]);
-            const int64_t i1 = wrapped(a.lo[1] + u1 + ra[f].k1, a.per[1]);
-            const int64_t i2 = wrapped(a.lo[2] + u2 + ra[f].k2, a.per[2]);
-            v = a.x[((i0 * a.d1 + i1) * a.d2 + i2) * two_nc + ra[f].el];
-          } else if (ok && ra[f].kind == 1) {
-            v = a.Y[ybase + ra[f].col];
-          }
-          av[f] = v;
+          // both indices formed without branches (a branch here cost a
+          // wait on the ring's loads)
+          const int64_t i0 = wrapped(a.lo[0] + u0 + ra[f].k0, a.per[0]);
+          const int64_t i1 = wrapped(a.lo[1] + u1 + ra[f].k1, a.per[1]);
+          const int64_t i2 = wrapped(a.lo[2] + u2 + ra[f].k2, a.per[2]);
+          const int64_t xi = ((i0 * a.d1 + i1) * a.d2 + i2) * two_nc + ra[f].el;
+          av[f] = src[f][on ? (ax_[f] ? xi : ybase + ra[f].col) : 0];
         }
         const bool onb = ok && cb[f] >= 0;
-        const float w = a.Y[onb ? ybase + cb[f] : 0];
-        bv[f] = onb ? w : 0.f;
+        bv[f] = a.Y[onb ? ybase + cb[f] : 0];
       }
       q += 4;
       ybase += 4 * two_l;
@@ -184,15 +181,16 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
     float av[PF][2], bv[PF][2];
 #pragma unroll
     for (int r = 0; r < PF; ++r) fetch(av[r], bv[r]);
+    // whole blocks of PF steps: steps past the range's end are masked
     for (int64_t q0 = q_begin; q0 < q_end; q0 += 4 * PF) {
 #pragma unroll
       for (int r = 0; r < PF; ++r) {
-        if (q0 + 4 * r >= q_end) break;
+        const bool ok = q0 + 4 * r + g < q_end;
         double ad[2], bd[2];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-          ad[f] = (double)av[r][f];
-          bd[f] = (double)bv[r][f];
+          ad[f] = (double)(av[r][f] * (ok && on_[f] ? 1.f : 0.f));
+          bd[f] = (double)(bv[r][f] * (ok && cb[f] >= 0 ? 1.f : 0.f));
         }
 #pragma unroll
         for (int f = 0; f < 2; ++f)
