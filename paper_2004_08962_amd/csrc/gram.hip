@@ -284,15 +284,39 @@ __host__ __device__ inline void cell_box(const CorrArgs& a, int cell, int64_t* s
 }
 
 // Work entries: each cell's points (row-major inside the cell box) in chunks
-// of a.chunk; one thread walks the cells in order (a few thousand at most).
-__global__ void corr_plan_kernel(CorrArgs a) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int e = 0;
-  for (int c = 0; c < a.ncell; ++c) {
+// of a.chunk, numbered cell by cell.  Each of the 256 threads takes a run of
+// consecutive cells, counts their entries, and writes them from its
+// exclusive prefix (a scan over the threads' counts in LDS).
+constexpr int kCorrPlanThreads = 256;
+__global__ __launch_bounds__(kCorrPlanThreads) void corr_plan_kernel(CorrArgs a) {
+  __shared__ int pre[kCorrPlanThreads];
+  const int tid = threadIdx.x;
+  const int per = (a.ncell + kCorrPlanThreads - 1) / kCorrPlanThreads;
+  const int c0 = min(a.ncell, tid * per), c1 = min(a.ncell, c0 + per);
+  auto count_of = [&](int c, int64_t* np) {
     int64_t st[3], ln[3];
     cell_box(a, c, st, ln);
-    const int64_t np = ln[0] * ln[1] * ln[2];
-    const int cnt = (int)((np + a.chunk - 1) / a.chunk);
+    *np = ln[0] * ln[1] * ln[2];
+    return (int)((*np + a.chunk - 1) / a.chunk);
+  };
+  int mine = 0;
+  for (int c = c0; c < c1; ++c) {
+    int64_t np;
+    mine += count_of(c, &np);
+  }
+  pre[tid] = mine;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele), then shift to exclusive
+  for (int off = 1; off < kCorrPlanThreads; off <<= 1) {
+    const int v = tid >= off ? pre[tid - off] : 0;
+    __syncthreads();
+    pre[tid] += v;
+    __syncthreads();
+  }
+  int e = pre[tid] - mine;
+  for (int c = c0; c < c1; ++c) {
+    int64_t np;
+    const int cnt = count_of(c, &np);
     a.cell_ent[2 * c] = e;
     a.cell_ent[2 * c + 1] = cnt;
     for (int i = 0; i < cnt; ++i, ++e) {
@@ -676,7 +700,7 @@ static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, s
     a.cell_ent = reinterpret_cast<int*>(b + cp.off_cell_ent);
     a.part = reinterpret_cast<double*>(b + cp.off_part);
     a.cellsum = reinterpret_cast<double*>(b + cp.off_cellsum);
-    hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(kCorrPlanThreads), 0, st, a);
     const int ngrp = corr_groups(a.nd_half, cp.T);
     const dim3 grid((unsigned)(rup((int64_t)a.nent, 8) * ngrp));
     switch (cp.T) {
