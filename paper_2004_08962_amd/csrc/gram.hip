@@ -268,6 +268,7 @@ struct CorrArgs {
   int* ent_cell;           // [nent] cell of each entry
   int64_t* ent_q;          // [nent][2] point range of each entry inside its cell box
   int* cell_ent;           // [ncell][2] first entry and entry count
+  int* multi_cell;         // cells with several entries, in cell order
   double* part;            // [nent][nd_half][ne]  real-embedding partial sums
   double* cellsum;         // [ncell][nd_half][ne] (cells with several entries)
 };
@@ -286,10 +287,11 @@ __host__ __device__ inline void cell_box(const CorrArgs& a, int cell, int64_t* s
 // Work entries: each cell's points (row-major inside the cell box) in chunks
 // of a.chunk, numbered cell by cell.  Each of the 256 threads takes a run of
 // consecutive cells, counts their entries, and writes them from its
-// exclusive prefix (a scan over the threads' counts in LDS).
+// exclusive prefix (a scan over the threads' counts in LDS); the cells with
+// several entries are listed the same way for the reduction.
 constexpr int kCorrPlanThreads = 256;
 __global__ __launch_bounds__(kCorrPlanThreads) void corr_plan_kernel(CorrArgs a) {
-  __shared__ int pre[kCorrPlanThreads];
+  __shared__ int pre[kCorrPlanThreads], pre_multi[kCorrPlanThreads];
   const int tid = threadIdx.x;
   const int per = (a.ncell + kCorrPlanThreads - 1) / kCorrPlanThreads;
   const int c0 = min(a.ncell, tid * per), c1 = min(a.ncell, c0 + per);
@@ -299,26 +301,32 @@ __global__ __launch_bounds__(kCorrPlanThreads) void corr_plan_kernel(CorrArgs a)
     *np = ln[0] * ln[1] * ln[2];
     return (int)((*np + a.chunk - 1) / a.chunk);
   };
-  int mine = 0;
+  int mine = 0, mine_multi = 0;
   for (int c = c0; c < c1; ++c) {
     int64_t np;
-    mine += count_of(c, &np);
+    const int cnt = count_of(c, &np);
+    mine += cnt;
+    mine_multi += cnt > 1;
   }
   pre[tid] = mine;
+  pre_multi[tid] = mine_multi;
   __syncthreads();
-  // inclusive scan (Hillis-Steele), then shift to exclusive
+  // inclusive scans (Hillis-Steele), then shifted to exclusive
   for (int off = 1; off < kCorrPlanThreads; off <<= 1) {
     const int v = tid >= off ? pre[tid - off] : 0;
+    const int vm = tid >= off ? pre_multi[tid - off] : 0;
     __syncthreads();
     pre[tid] += v;
+    pre_multi[tid] += vm;
     __syncthreads();
   }
-  int e = pre[tid] - mine;
+  int e = pre[tid] - mine, mi = pre_multi[tid] - mine_multi;
   for (int c = c0; c < c1; ++c) {
     int64_t np;
     const int cnt = count_of(c, &np);
     a.cell_ent[2 * c] = e;
     a.cell_ent[2 * c + 1] = cnt;
+    if (cnt > 1) a.multi_cell[mi++] = c;
     for (int i = 0; i < cnt; ++i, ++e) {
       a.ent_cell[e] = c;
       a.ent_q[2 * e] = (int64_t)i * a.chunk;
@@ -532,11 +540,11 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   }
 }
 
-// Cells split over several entries: their partial sums added in entry order.
+// Cells split over several entries (grid axis y walks their list): their
+// partial sums added in entry order.
 __global__ __launch_bounds__(256) void corr_reduce_kernel(CorrArgs a) {
-  const int cell = blockIdx.y;
+  const int cell = a.multi_cell[blockIdx.y];
   const int first = a.cell_ent[2 * cell], cnt = a.cell_ent[2 * cell + 1];
-  if (cnt <= 1) return;
   const int64_t per = (int64_t)a.nd_half * a.ne;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
@@ -595,7 +603,8 @@ constexpr int kCorrMaxCoils = 32;  // T <= 4 tiles of 16 real components
 struct CorrPlan {
   CorrArgs a;
   int T;
-  size_t off_ent_cell, off_ent_q, off_cell_ent, off_part, off_cellsum, total;
+  size_t off_ent_cell, off_ent_q, off_cell_ent, off_multi, off_part, off_cellsum, total;
+  int multi;  // cells with several entries
 };
 
 bool corr_plan(const Geo& g, CorrPlan* p) {
@@ -646,6 +655,8 @@ bool corr_plan(const Geo& g, CorrPlan* p) {
   p->off_ent_cell = take((size_t)nent * sizeof(int));
   p->off_ent_q = take(2 * (size_t)nent * sizeof(int64_t));
   p->off_cell_ent = take(2 * (size_t)a.ncell * sizeof(int));
+  p->off_multi = take((size_t)a.ncell * sizeof(int));
+  p->multi = (int)multi;
   p->off_part = take((size_t)nent * per);
   p->off_cellsum = take(multi > 0 ? (size_t)a.ncell * per : 0);
   p->total = off;
@@ -698,6 +709,7 @@ static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, s
     a.ent_cell = reinterpret_cast<int*>(b + cp.off_ent_cell);
     a.ent_q = reinterpret_cast<int64_t*>(b + cp.off_ent_q);
     a.cell_ent = reinterpret_cast<int*>(b + cp.off_cell_ent);
+    a.multi_cell = reinterpret_cast<int*>(b + cp.off_multi);
     a.part = reinterpret_cast<double*>(b + cp.off_part);
     a.cellsum = reinterpret_cast<double*>(b + cp.off_cellsum);
     hipLaunchKernelGGL(corr_plan_kernel, dim3(1), dim3(kCorrPlanThreads), 0, st, a);
@@ -710,8 +722,9 @@ static int32_t launch_gram_box(const Geo& g, const void* x, void* G, void* ws, s
       default: hipLaunchKernelGGL(corr_kernel<4>, grid, dim3(256), 0, st, a); break;
     }
     const int64_t per = (int64_t)a.nd_half * a.ne;
-    hipLaunchKernelGGL(corr_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(per, 256), 1024), a.ncell),
-                       dim3(256), 0, st, a);
+    if (cp.multi > 0)
+      hipLaunchKernelGGL(corr_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(per, 256), 1024), cp.multi),
+                         dim3(256), 0, st, a);
     const int64_t tot = (int64_t)g.k[0] * g.k[1] * g.k[2] * a.nd_half * g.nc * g.nc;
     hipLaunchKernelGGL(corr_assemble_kernel, dim3((unsigned)std::min<int64_t>(cdiv(tot, 256), 65536)), dim3(256), 0,
                        st, a, g.n, reinterpret_cast<double2*>(G));
