@@ -862,9 +862,16 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
   // Each sweep's convergence sums reach the host through pinned memory of
   // this host thread while the GPU already runs the next sweep's opening
   // round, which writes only the round buffers (no effect on A or V when
-  // the host then stops).
+  // the host then stops).  The memory is coherent and mapped: sums_kernel
+  // stores into it directly (a copy launch after it took about 12 us per
+  // sweep), and the event's system-scope release makes the stores visible
+  // to the host once the event has completed.
   static thread_local double* h_sums = nullptr;
-  if (!h_sums) HICU_HIP_TRY(hipHostMalloc((void**)&h_sums, 4 * sizeof(double), hipHostMallocDefault));
+  static thread_local double* h_sums_dev = nullptr;  // device address of h_sums
+  if (!h_sums)
+    HICU_HIP_TRY(hipHostMalloc((void**)&h_sums, 4 * sizeof(double),
+                               hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
+  if (!h_sums_dev) HICU_HIP_TRY(hipHostGetDevicePointer((void**)&h_sums_dev, h_sums, 0));
   struct Event {
     hipEvent_t e = nullptr;
     ~Event() {
@@ -888,10 +895,9 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
                          idbuf[par(r)], Sbuf[par(r)], tol_inner, (const double*)dfloor, last ? part : nullptr);
       cur ^= 1;
     }
-    hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nwg, dsums);
+    hipLaunchKernelGGL(sums_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nwg, h_sums_dev);
     HICU_HIP_TRY(hipGetLastError());
     ++sweeps;
-    HICU_HIP_TRY(hipMemcpyAsync(h_sums, dsums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HICU_HIP_TRY(hipEventRecord(done.e, st));
     opening();  // the next sweep's, on the chance that this one has not converged
     HICU_HIP_TRY(hipGetLastError());
