@@ -161,8 +161,9 @@ int32_t hicu_set_gram_route(int32_t route);
  * Synchronous on `stream` (the convergence test reads two sums per sweep,
  * through 32 bytes of pinned host memory that the first call on a host
  * thread allocates and keeps until the process ends).
- * Returns HICU_ERR_NOCONV if 40 sweeps do not reach relative off-diagonal
- * size 1e-14 (outputs are still written).
+ * Returns HICU_ERR_NOCONV if 40 sweeps neither bring the off-diagonal
+ * Frobenius norm below 1e-13 of the whole nor reach the rounding floor
+ * (below 1e-10 and no longer halving per sweep); outputs are still written.
  * ------------------------------------------------------------------------ */
 size_t hicu_nullspace_workspace_bytes(int32_t n);
 int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G_dev, const void* V0_dev,
