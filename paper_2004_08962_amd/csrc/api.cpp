@@ -354,6 +354,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
   float2* x = reinterpret_cast<float2*>(xout);
   float2* g = reinterpret_cast<float2*>(at(ws, pl.o_g));
   double* sc = reinterpret_cast<double*>(at(ws, pl.o_sc));
+  HostWait wait;
   // A non-finite input is rejected before anything is written.
   {
     unsigned long long bad = 0;
@@ -426,7 +427,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
     if (cnt > 0) {
       HICU_HIP_TRY(hipMemcpyAsync(hs.data() + 3 * step0, sc + 3 * step0, (size_t)cnt * 3 * sizeof(double),
                                   hipMemcpyDeviceToHost, st));
-      HICU_HIP_TRY(hipStreamSynchronize(st));
+      HICU_HIP_TRY(wait.stream(st));
     }
     for (int64_t s = step0; s < step; ++s) {
       if (!std::isfinite(hs[3 * s]) || !std::isfinite(hs[3 * s + 1]) || !std::isfinite(hs[3 * s + 2]))
@@ -441,7 +442,7 @@ int32_t hicu_solve(const hicu_geom* gm, const void* x0, const uint8_t* mask, con
   // Steps not run after a stop keep zero scalars in the trace.
   if (trace)
     for (int64_t s = step; s < total_steps; ++s) trace[s] = hicu_trace{-1, -1, -1, 0, 0.0, 0.0, 0.0};
-  HICU_HIP_TRY(hipStreamSynchronize(st));
+  HICU_HIP_TRY(wait.stream(st));
   return status;
 }
 

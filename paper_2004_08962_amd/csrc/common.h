@@ -24,6 +24,35 @@ namespace hicu {
     if (_s < 0) return _s;                                  \
   } while (0)
 
+// Host waits that poll an event instead of blocking in the runtime.  A
+// solve waits on the device about a hundred times (each Jacobi sweep's
+// convergence sums, each outer iteration's step scalars); a blocking wait
+// that falls back to an interrupt adds the host's wake-up latency to every
+// one of them.  Polling keeps the calling thread busy during the wait.
+struct HostWait {
+  hipEvent_t e = nullptr;
+  HostWait() = default;
+  HostWait(const HostWait&) = delete;
+  HostWait& operator=(const HostWait&) = delete;
+  ~HostWait() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t init() { return e ? hipSuccess : hipEventCreateWithFlags(&e, hipEventDisableTiming); }
+  // until the last record of e has completed
+  hipError_t poll() const {
+    hipError_t q;
+    while ((q = hipEventQuery(e)) == hipErrorNotReady) {
+    }
+    return q;
+  }
+  // until everything queued on st so far has completed
+  hipError_t stream(hipStream_t st) {
+    hipError_t r = init();
+    if (r == hipSuccess) r = hipEventRecord(e, st);
+    return r == hipSuccess ? poll() : r;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Canonical (right-aligned, 3-axis) geometry
 // ---------------------------------------------------------------------------

@@ -872,13 +872,8 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
     HICU_HIP_TRY(hipHostMalloc((void**)&h_sums, 4 * sizeof(double),
                                hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable));
   if (!h_sums_dev) HICU_HIP_TRY(hipHostGetDevicePointer((void**)&h_sums_dev, h_sums, 0));
-  struct Event {
-    hipEvent_t e = nullptr;
-    ~Event() {
-      if (e) (void)hipEventDestroy(e);
-    }
-  } done;
-  HICU_HIP_TRY(hipEventCreateWithFlags(&done.e, hipEventDisableTiming));
+  HostWait done;
+  HICU_HIP_TRY(done.init());
   auto opening = [&]() {
     // opening round: blocks (2 j, 2 j + 1) with all their index pairs
     hipLaunchKernelGGL(pair_eig_kernel, dim3(npair), dim3(1024), 0, st, (const double2*)Abuf[cur], np, nb, -1,
@@ -901,7 +896,7 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
     HICU_HIP_TRY(hipEventRecord(done.e, st));
     opening();  // the next sweep's, on the chance that this one has not converged
     HICU_HIP_TRY(hipGetLastError());
-    HICU_HIP_TRY(hipEventSynchronize(done.e));
+    HICU_HIP_TRY(done.poll());
     sums[0] = h_sums[0];
     sums[1] = h_sums[1];
     const double rel = sums[1] > 0.0 ? std::sqrt(sums[0] / sums[1]) : 0.0;
@@ -927,7 +922,7 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
     hipLaunchKernelGGL(copy_vals_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, (const double*)vals,
                        evals, n);
   HICU_HIP_TRY(hipGetLastError());
-  HICU_HIP_TRY(hipStreamSynchronize(st));
+  HICU_HIP_TRY(done.stream(st));
   return status;
 }
 

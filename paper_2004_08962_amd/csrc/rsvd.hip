@@ -578,7 +578,8 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
   if (rank == 0) {
     hipLaunchKernelGGL(identity_kernel, dim3((unsigned)cdiv((int64_t)n * n, 256)), dim3(256), 0, st, Q, n);
     HICU_HIP_TRY(hipGetLastError());
-    HICU_HIP_TRY(hipStreamSynchronize(st));
+    HostWait w;
+    HICU_HIP_TRY(w.stream(st));
     return HICU_OK;
   }
   if (ell < rank || ell > n) return HICU_ERR_ARG;
@@ -700,7 +701,8 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
       HICU_TRY(launch_apply<32>(Wr, n, rank, Q, st));
     }
   }
-  HICU_HIP_TRY(hipStreamSynchronize(st));
+  HostWait w;
+  HICU_HIP_TRY(w.stream(st));
   return status;
 }
 
