@@ -143,7 +143,13 @@ int32_t hicu_nullspace(int32_t n, int32_t rank, const void* G, const void* V0, v
   if (rank < 0 || rank >= n) return HICU_ERR_RANK;
   if (!G || (!Q && !V && !evals)) return HICU_ERR_ARG;
   ProfScope ps("eig", (hipStream_t)stream);
-  return run_eig(n, rank, G, V0, Q, evals, V, sweeps, ws, ws_bytes, (hipStream_t)stream, false);
+  const int32_t s = run_eig(n, rank, G, V0, Q, evals, V, sweeps, ws, ws_bytes, (hipStream_t)stream, false);
+  // wait for the queued work unless the call was rejected before any launch
+  if (s == HICU_OK || s == HICU_ERR_NOCONV || s == HICU_ERR_NONFINITE) {
+    HostWait w;
+    HICU_HIP_TRY(w.stream((hipStream_t)stream));
+  }
+  return s;
 }
 
 size_t hicu_nullspace_rsvd_workspace_bytes(const hicu_geom* gm, int32_t rank, int32_t ell) {
@@ -166,8 +172,14 @@ int32_t hicu_nullspace_rsvd(const hicu_geom* gm, const void* x, int32_t rank, in
   const int l = ell == 0 ? default_sketch(rank, g.n) : ell;
   if (rank > 0 && (l < rank || l > g.n)) return HICU_ERR_ARG;
   ProfScope ps("rsvd", (hipStream_t)stream);
-  return run_rsvd(g, x, rank, l, seed, outer, sid, reinterpret_cast<float2*>(Q), sv, sweeps, ws, ws_bytes,
-                  (hipStream_t)stream, true);
+  const int32_t s = run_rsvd(g, x, rank, l, seed, outer, sid, reinterpret_cast<float2*>(Q), sv, sweeps, ws,
+                             ws_bytes, (hipStream_t)stream, true);
+  // wait for the queued work unless the call was rejected before any launch
+  if (s == HICU_OK || s == HICU_ERR_NOCONV || s == HICU_ERR_NONFINITE) {
+    HostWait w;
+    HICU_HIP_TRY(w.stream((hipStream_t)stream));
+  }
+  return s;
 }
 
 int32_t hicu_sketch(int32_t n, int32_t ell, uint64_t seed, uint32_t outer, uint32_t sid, void* Om, void* stream) {

@@ -922,7 +922,6 @@ int32_t run_eig(int n, int rank, const void* G, const void* V0, void* Q, double*
     hipLaunchKernelGGL(copy_vals_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, (const double*)vals,
                        evals, n);
   HICU_HIP_TRY(hipGetLastError());
-  HICU_HIP_TRY(done.stream(st));
   return status;
 }
 

@@ -19,7 +19,8 @@ size_t rsvd_workspace(const Geo& g, int rank, int ell);
 // Jacobi sweeps of its eigensolve.  basis = false resolves the singular
 // vectors of B only to the eigensolver's projector accuracy (enough when
 // only Q Q' is used); true resolves each of them, which fixes the
-// Householder basis.  Synchronous on st.
+// Householder basis.  Returns with the work queued on st (the public entry
+// point waits).
 int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, uint32_t outer, uint32_t sid,
                  float2* Q, double* sv, int32_t* sweeps, void* ws, size_t ws_bytes, hipStream_t st, bool basis);
 

@@ -578,8 +578,6 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
   if (rank == 0) {
     hipLaunchKernelGGL(identity_kernel, dim3((unsigned)cdiv((int64_t)n * n, 256)), dim3(256), 0, st, Q, n);
     HICU_HIP_TRY(hipGetLastError());
-    HostWait w;
-    HICU_HIP_TRY(w.stream(st));
     return HICU_OK;
   }
   if (ell < rank || ell > n) return HICU_ERR_ARG;
@@ -701,8 +699,6 @@ int32_t run_rsvd(const Geo& g, const void* x, int rank, int ell, uint64_t seed, 
       HICU_TRY(launch_apply<32>(Wr, n, rank, Q, st));
     }
   }
-  HostWait w;
-  HICU_HIP_TRY(w.stream(st));
   return status;
 }
 
