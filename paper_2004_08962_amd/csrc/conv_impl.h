@@ -416,7 +416,12 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, const int64_t bx, c
   constexpr int PD = SPLIT ? 1 : prefetch_distance<FM, FN>();
   constexpr int NB = PD + 1;
   static_assert(NB % 2 == 0, "ring size must be even");
+  // A wave whose columns all lie past the launch's last column (the tail
+  // of the last column block) has nothing to accumulate: it skips the
+  // k-loop (its accumulators stay zero and are never stored).
+  const bool live_cols = by * BC + wc * FN * 16 < D * a.coutr;
   auto compute_chunk_flat = [&](const int chg) {
+    if (!live_cols) return;
     FragA<PREC, FM> fa[2];
     FragB<PREC, FN> fb[NB];
     const BE* bhi0 = reinterpret_cast<const BE*>(a.B) + (size_t)chg * total * wstep;
